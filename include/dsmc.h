@@ -1,0 +1,213 @@
+/*
+ * dsmc.h -- C ABI of the MI355X DSMC micro-solver for force-driven, low-speed
+ * rarefied flow between parallel plates (arXiv 2311.14140).
+ *
+ * The solver is the micro model of the paper's micro-macro-surrogate method:
+ * DSMC (Sec. 1 and 2, Bird's method) for a monatomic gas between two plates
+ * held at a fixed temperature and driven by a small acceleration parallel to
+ * them (Sec. 2.1).  Its outputs are the fields the surrogates are trained on:
+ * velocity and shear-stress profiles averaged over windows of time steps
+ * (Sec. 2.2, Eqs. 11-13; Sec. 3: 100-step averages), plus density,
+ * temperature, heat flux and the mass flow rate.
+ *
+ * Units follow the paper's statement of the problem: Kn is the hard-sphere
+ * mean free path over the plate gap H (Sec. 1 defines Kn = lambda / L), the
+ * body force is the dimensionless F = F' H / v0^2 of Eq. 6, the wall
+ * temperature is relative to the reference temperature, and time is in
+ * H / sqrt(k T_ref / m).  Returned velocities, heat fluxes and the mass flow
+ * are over v0 = sqrt(2 k T_ref / m) and stresses over P0 = n k T_ref, the
+ * normalisation of Eq. 6.
+ *
+ * Conventions for every call:
+ *   - Status codes: DSMC_OK (0) or a negative DSMC_ERR_*; nothing aborts or
+ *     throws across the ABI.
+ *   - Out-parameters are written only on success (*out handles are set to
+ *     NULL on failure).
+ *   - Pointers documented as "host" are ordinary host memory owned by the
+ *     caller; pointers documented as "device" are device memory on the
+ *     current HIP device, borrowed by the library.
+ *   - A handle is used by one host thread at a time; distinct handles are
+ *     independent.  dsmc_step and dsmc_group_step only enqueue work; errors
+ *     raised on the device surface at the next synchronising call
+ *     (dsmc_sample, dsmc_get_state, dsmc_get_cells, dsmc_sync).
+ */
+#ifndef DSMC_H_
+#define DSMC_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DSMC_OK = 0,
+    DSMC_ERR_INVALID_ARG = -1,  /* bad parameter or pointer; nothing was done */
+    DSMC_ERR_OUT_OF_MEMORY = -2,/* device allocation failed or arena too small */
+    DSMC_ERR_DEVICE = -3,       /* a HIP call failed */
+    DSMC_ERR_STATE = -4,        /* call not allowed in the handle's state */
+    DSMC_ERR_NUMERIC = -5       /* non-finite velocity or lost particle seen on device */
+};
+
+/* Precision and collision scheme. */
+enum {
+    /* FP64 state and arithmetic, collisions sequential per cell in candidate
+     * order, every operation in a fixed IEEE order with no FMA contraction:
+     * reproduces the reference recipe bit for bit. */
+    DSMC_FP64_DETERMINISTIC = 0,
+    /* FP32 positions and velocities, FP64 accumulators; collisions of a cell
+     * processed 64 candidates at a time by one wavefront (NTC in
+     * distribution: each candidate pair is drawn and accepted exactly as in
+     * the sequential scheme, only non-conflicting candidates may run
+     * together).  Deterministic run to run and independent of batching. */
+    DSMC_FP32_FAST = 1,
+    /* The DSMC_FP32_FAST scheme with FP64 state. */
+    DSMC_FP64_FAST = 2
+};
+
+/* Phase mask for tests (dsmc_params.debug_phase_mask); 0 means all. */
+enum {
+    DSMC_PHASE_MOVE = 1,
+    DSMC_PHASE_SORT = 2,
+    DSMC_PHASE_COLLIDE = 4,
+    DSMC_PHASE_SAMPLE = 8,
+    DSMC_PHASE_ALL = 15
+};
+
+typedef struct dsmc_params {
+    uint32_t struct_size;       /* = sizeof(dsmc_params); ABI guard */
+    int32_t precision;          /* DSMC_FP64_DETERMINISTIC | DSMC_FP32_FAST | DSMC_FP64_FAST */
+    double kn;                  /* hard-sphere lambda / H, finite, > 0 */
+    double body_force;          /* F of Eq. 6 along x, finite */
+    double wall_temperature;    /* T_w / T_ref, finite, > 0 */
+    double dt;                  /* time step; <= 0 selects 0.2 min(lambda, H) / sqrt(2) */
+    int32_t n_cells;            /* sampling cells across the gap, >= 1 */
+    int32_t particles_per_cell; /* initial particles per sampling cell, >= 1 */
+    int32_t n_sub;              /* collision cells per sampling cell, >= 1 (1 = plain) */
+    uint32_t debug_phase_mask;  /* DSMC_PHASE_* subset for tests; 0 = all */
+    int64_t n_transient;        /* steps before sampling starts, >= 0 */
+    uint64_t seed;              /* key of every random stream */
+} dsmc_params;
+
+/* Estimators over the current window (all arrays host, caller-owned, length
+ * n_cells; any array pointer may be NULL to skip it). */
+typedef struct dsmc_moments {
+    int32_t n_cells;            /* in: capacity of the arrays (>= the handle's cells) */
+    int32_t pad_;
+    int64_t n_sampled_steps;    /* out: sampled steps K in the window */
+    double *n;                  /* density over the mean density */
+    double *ux, *uy, *uz;       /* mean velocity over v0 */
+    double *T;                  /* temperature over T_ref */
+    double *pxy;                /* shear stress P_xy over P0 */
+    double *qx, *qy;            /* heat flux over P0 v0 */
+    double *raw_sums;           /* optional: n_cells*n_sub*12 FP64 sums per collision cell:
+                                   1, vx, vy, vz, vx2, vy2, vz2, vxvy, vxvz, vyvz, v2vx, v2vy */
+    double mass_flow;           /* out: integral of n u_x dy over (n_mean H v0); NaN if K = 0 */
+    int64_t n_collisions;       /* out: accepted collisions in the window */
+} dsmc_moments;
+
+typedef struct dsmc_handle dsmc_handle;
+typedef struct dsmc_group dsmc_group;
+
+/* Fill *p with the library defaults (Kn 1, F 0, T_w 1, 100 cells x 50,
+ * default dt, FP64 deterministic). */
+int dsmc_params_init(dsmc_params *p);
+
+/* Device bytes an instance with these parameters needs from an arena. */
+int dsmc_footprint_bytes(const dsmc_params *p, uint64_t *bytes);
+
+/* Create one solver instance and enqueue its initial state: every sampling
+ * cell gets exactly particles_per_cell particles, uniform inside it, with
+ * Maxwellian velocities at the wall temperature.
+ *   stream: a hipStream_t borrowed for all of the instance's work, or NULL
+ *           for the legacy default stream; must outlive the handle.
+ *   arena:  device memory of at least dsmc_footprint_bytes bytes, borrowed
+ *           (must outlive the handle), or NULL for the library to allocate.
+ * Errors: INVALID_ARG for bad parameters, OUT_OF_MEMORY, DEVICE. */
+int dsmc_create(const dsmc_params *p, void *stream, void *arena, uint64_t arena_bytes,
+                dsmc_handle **out);
+
+/* Enqueue n_steps >= 0 DSMC steps (move with body force and diffuse walls;
+ * stable sort by collision cell; NTC hard-sphere collisions; sampling after
+ * the transient).  Asynchronous.  STATE if the handle belongs to a group. */
+int dsmc_step(dsmc_handle *h, int64_t n_steps);
+
+/* Synchronise, then fill *out with the estimators of the current window;
+ * if reset_window != 0 start a new window afterwards.  Calling it with reset
+ * every 100 steps gives the paper's training samples (Sec. 3).
+ * NUMERIC if the device flagged a non-finite velocity or a lost particle. */
+int dsmc_sample(dsmc_handle *h, dsmc_moments *out, int reset_window);
+
+/* Wait for the handle's enqueued work; surfaces device errors. */
+int dsmc_sync(dsmc_handle *h);
+
+/* Release the handle (NULL-safe).  Removes it from its group if any. */
+int dsmc_destroy(dsmc_handle *h);
+
+/* Copy the particle state in slot order to host arrays of N elements (double
+ * for the FP64 modes, float for FP32) and the steps completed.  Any pointer
+ * may be NULL.  Synchronises. */
+int dsmc_get_state(dsmc_handle *h, void *y, void *vx, void *vy, void *vz, int32_t *cell,
+                   uint64_t *step);
+
+/* Replace the particle state (same layout as dsmc_get_state; NULL leaves an
+ * array unchanged) and the step counter.  With dsmc_set_cells it restores a
+ * checkpoint exactly. */
+int dsmc_set_state(dsmc_handle *h, const void *y, const void *vx, const void *vy,
+                   const void *vz, const int32_t *cell, uint64_t step);
+
+/* Per collision cell (n_cells*n_sub each, host): crmax, the NTC remainder,
+ * particle count and slot offset after the last sort.  NULL skips. */
+int dsmc_get_cells(dsmc_handle *h, double *crmax, double *rem, int32_t *count,
+                   int32_t *offset);
+int dsmc_set_cells(dsmc_handle *h, const double *crmax, const double *rem,
+                   const int32_t *count, const int32_t *offset);
+
+/* Particles, collision cells and derived constants of a handle:
+ * out[0..5] = dt, g (= 2F), K_ntc, crmax0, cells per unit length, lambda. */
+int dsmc_info(const dsmc_handle *h, int32_t *n_particles, int32_t *n_coll_cells,
+              double *constants6);
+
+/* Per-phase timing: run n_steps >= 1 steps of the handle (real steps, launched
+ * one kernel at a time on its stream) with HIP events around every kernel and
+ * write the summed device milliseconds of each kernel to phase_ms[8] (host):
+ * move+histogram, column sums, scan, column prefix, scatter, collide+sample,
+ * and [6] = all kernels, [7] = wall time of the whole run.  Synchronises. */
+int dsmc_profile_step(dsmc_handle *h, int64_t n_steps, double *phase_ms);
+
+const char *dsmc_status_string(int status);
+/* Last error message of a handle (or of the library when h is NULL). */
+const char *dsmc_last_error(const dsmc_handle *h);
+
+/* ---------------------------------------------------------------- batching
+ * A group runs many independent instances of one precision together: each
+ * phase of a step is one launch over all members, and chunks of steps are
+ * replayed from a captured HIP graph.  Per-instance arithmetic and ordering
+ * are the same as alone, so results do not depend on the group's make-up. */
+int dsmc_group_create(void *stream, dsmc_group **out);
+/* Add an instance (INVALID_ARG if it already belongs to a group or its
+ * precision differs from the group's). */
+int dsmc_group_add(dsmc_group *g, dsmc_handle *h);
+int dsmc_group_remove(dsmc_group *g, dsmc_handle *h);
+/* Enqueue n_steps for every member. */
+int dsmc_group_step(dsmc_group *g, int64_t n_steps);
+int dsmc_group_sync(dsmc_group *g);
+int dsmc_group_size(const dsmc_group *g, int32_t *n_members);
+int dsmc_group_destroy(dsmc_group *g);
+
+/* Launch-shape tuning of a group: tile_mult multiplies each member's base
+ * particle tile (the slots one move or scatter workgroup walks; 1, 2, 4, ...)
+ * and cells_per_block sets the collision cells one fast-collide workgroup
+ * stages on chip; 0 keeps the automatic choice.  Results do not depend on
+ * either. */
+int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t cells_per_block);
+/* Time candidate launch shapes on the group for a few steps each (the steps
+ * are real steps of the members) and keep the fastest; writes the choice to
+ * *tile_mult / *cells_per_block (either may be NULL). */
+int dsmc_group_autotune(dsmc_group *g, int32_t *tile_mult, int32_t *cells_per_block);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSMC_H_ */

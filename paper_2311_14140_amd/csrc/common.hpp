@@ -1,0 +1,53 @@
+// common.hpp -- device-resident descriptors shared by the kernels and the
+// host runtime of the DSMC library.
+#pragma once
+#include <stdint.h>
+
+namespace dsmc {
+
+constexpr int kMoments = 12;       // 1, vx, vy, vz, vx2, vy2, vz2, vxvy, vxvz, vyvz, v2vx, v2vy
+constexpr int kEstPerCell = 8;     // n, ux, uy, uz, T, pxy, qx, qy
+constexpr int kParticleThreads = 256;  // threads of the move and scatter kernels
+constexpr int kColThreads = 256;       // cells per workgroup of the column-scan kernels
+constexpr int kScanThreads = 1024;     // threads of the per-instance scan kernel
+constexpr int kSegTiles = 32;          // tiles per column-scan segment
+constexpr int kClaimTable = 1024;      // per-wavefront claim table of the fast collide
+constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
+
+// Scalars an instance keeps on the device so that a step is the same launch
+// sequence every time (and can be replayed from a graph).
+struct DevScalars {
+    int64_t step_done;            // steps completed
+    int64_t n_sampled;            // sampled steps in the window
+    unsigned long long n_coll;    // accepted collisions in the window
+    unsigned long long n_hits;    // wall hits since creation
+    int32_t status;               // bit 0: non-finite velocity, bit 1: particle count lost
+    int32_t pad_;
+};
+
+// Everything a kernel needs to know about one instance.  Particle arrays are
+// structure-of-arrays: buf[b][0..3] = y, vx, vy, vz of buffer b.  After step
+// s the state lives in buffer (s & 1): the move of step s works in place on
+// buffer ((s - 1) & 1) and the stable scatter writes buffer (s & 1).
+struct InstDesc {
+    int32_t N, C, Cc, n_sub;           // particles, sampling cells, collision cells, Cc / C
+    int32_t tiles, tile_items, nseg, ppc;  // particle tiles, items per tile, scan segments
+    double H, dt, g, kntc, crmax0, sqrt_tw, inv_dy, pad0_;
+    int64_t n_transient;
+    uint32_t key0, key1;
+    uint32_t phase_mask;
+    int32_t pad1_;
+    void* buf[2][4];
+    int32_t* cell;     // N: collision cell of each slot (pre-sort order)
+    int32_t* counts;   // tiles * Cc: per-tile histogram, then per-tile scatter bases
+    int32_t* segsum;   // nseg * Cc: per-segment column sums, then segment bases
+    int32_t* count;    // Cc
+    int32_t* offset;   // Cc
+    double* crmax;     // Cc
+    double* rem;       // Cc
+    double* acc;       // Cc * kMoments
+    double* est;       // kEstPerCell * C + 2 (mass flow, sampled steps)
+    DevScalars* sc;
+};
+
+}  // namespace dsmc

@@ -1,0 +1,833 @@
+// kernels.hip -- DSMC hot path for gfx950 (MI355X).
+//
+// One step of force-driven parallel-plate DSMC (the micro model of arXiv
+// 2311.14140, Sec. 2.1: gas between isothermal plates under a body force
+// parallel to them) is five phases, each one launch over every instance of a
+// group:
+//   1. k_move_hist   free flight under the body force, diffuse wall
+//                    re-emission, collision-cell index, per-tile LDS histogram
+//   2. k_colsum      per-segment column sums of the tile histograms
+//   3. k_scan        per-instance exclusive scan: cell counts and offsets,
+//                    segment bases; advances the step counter
+//   4. k_colprefix   per-tile scatter bases (column prefix within a segment)
+//   5. k_scatter     stable scatter of the SoA records into cell order
+//   6. k_collide_*   NTC hard-sphere collisions per collision cell, fused with
+//                    the FP64 moment sums of the sampling steps
+// Everything is HBM-bound streaming over structure-of-arrays particle
+// records; there is no dense contraction anywhere, so no MFMA.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "rng.hpp"
+
+#pragma clang fp contract(off)
+
+namespace dsmc {
+
+namespace {
+
+constexpr unsigned kPhaseMove = 1, kPhaseSort = 2, kPhaseCollide = 4, kPhaseSample = 8;
+
+template <class R> struct P4 {
+    R* y;
+    R* vx;
+    R* vy;
+    R* vz;
+};
+
+template <class R> __device__ __forceinline__ P4<R> particles(const InstDesc& d, int b) {
+    return P4<R>{(R*)d.buf[b][0], (R*)d.buf[b][1], (R*)d.buf[b][2], (R*)d.buf[b][3]};
+}
+
+__device__ __forceinline__ unsigned long long lanes_below(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// ------------------------------------------------------------------ init
+// Initial state (the paper's gas at rest between the plates, Sec. 2.1):
+// particle p sits in sampling cell p / ppc, uniform inside it, with a
+// Maxwellian velocity at T_w.  Drawn in FP64 for every precision, then
+// stored in the instance's precision.
+template <class R>
+__global__ void k_init(const InstDesc* __restrict__ descs) {
+    const InstDesc& d = descs[0];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < d.N) {
+        const int c = p / d.ppc;
+        const double dy = d.H / (double)d.C;
+        Stream st(d.key0, d.key1, 0u, (uint32_t)p, 0u, kTagInit);
+        double ua, ub;
+        Num<double>::uni2(st.next(), ua, ub);
+        const double y = ((double)c + (1.0 - ua)) * dy;
+        double vx, vy, vz, unused;
+        normal_pair<double>(st, d.sqrt_tw, vx, vy);
+        normal_pair<double>(st, d.sqrt_tw, vz, unused);
+        P4<R> b = particles<R>(d, 0);
+        b.y[p] = (R)y;
+        b.vx[p] = (R)vx;
+        b.vy[p] = (R)vy;
+        b.vz[p] = (R)vz;
+        d.cell[p] = 0;
+    }
+    if (p < d.Cc) {
+        d.crmax[p] = d.crmax0;
+        d.rem[p] = 0.0;
+        d.count[p] = 0;
+        d.offset[p] = 0;
+        for (int m = 0; m < kMoments; ++m) d.acc[(size_t)p * kMoments + m] = 0.0;
+    }
+    if (p == 0) {
+        d.sc->step_done = 0;
+        d.sc->n_sampled = 0;
+        d.sc->n_coll = 0;
+        d.sc->n_hits = 0;
+        d.sc->status = 0;
+    }
+}
+
+// ------------------------------------------------------------------ move
+// Free flight for dt under the acceleration g along x, followed exactly per
+// segment; whenever the particle reaches a plate before its time runs out it
+// is re-emitted from the wall Maxwellian at T_w (normal speed
+// sqrt(-2 T_w ln U), tangential components a polar normal pair), which may
+// happen several times in one step.  Returns the number of wall hits.
+template <class R>
+__device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32_t slot, R& y,
+                                        R& vx, R& vy, R& vz) {
+    const R H = (R)d.H, g = (R)d.g, sd = (R)d.sqrt_tw;
+    R t = (R)d.dt;
+    int h = 0;
+    for (;;) {
+        R tw;
+        if (vy > R(0))
+            tw = (H - y) / vy;
+        else if (vy < R(0))
+            tw = (R(0) - y) / vy;
+        else
+            tw = (R)INFINITY;
+        if (tw >= t) {
+            y = y + vy * t;
+            vx = vx + g * t;
+            break;
+        }
+        const bool top = vy > R(0);
+        y = top ? H : R(0);
+        t = t - tw;
+        Stream st(d.key0, d.key1, step, slot, (uint32_t)h, kTagWall);
+        R ua, ub;
+        Num<R>::uni2(st.next(), ua, ub);
+        const R vn = Num<R>::sqrt(R(-2) * Num<R>::log(ua)) * sd;
+        normal_pair<R>(st, sd, vx, vz);
+        vy = top ? -vn : vn;
+        ++h;
+    }
+    if (y < R(0)) y = R(0);
+    if (y > H) y = H;
+    return h;
+}
+
+template <class R> __device__ __forceinline__ int cell_of(const InstDesc& d, R y) {
+    int c = (int)(y * (R)d.inv_dy);
+    if (c >= d.Cc) c = d.Cc - 1;
+    if (!(c >= 0)) c = 0;  // only reachable from a non-finite position
+    return c;
+}
+
+template <class R, bool kMove>
+__global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* __restrict__ descs,
+                                                               const int2* __restrict__ work) {
+    extern __shared__ int hist[];
+    __shared__ int blk_hits, blk_bad;
+    const int2 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int Cc = d.Cc;
+    for (int c = threadIdx.x; c < Cc; c += blockDim.x) hist[c] = 0;
+    if (threadIdx.x == 0) {
+        blk_hits = 0;
+        blk_bad = 0;
+    }
+    __syncthreads();
+    const int64_t s = d.sc->step_done + 1;
+    const P4<R> b = particles<R>(d, (int)((s - 1) & 1));
+    const int start = w.y * d.tile_items;
+    const int end = min(start + d.tile_items, d.N);
+    int hits = 0, bad = 0;
+    for (int p = start + (int)threadIdx.x; p < end; p += blockDim.x) {
+        int c;
+        if (kMove) {
+            R y = b.y[p], vx = b.vx[p], vy = b.vy[p], vz = b.vz[p];
+            const int h = move_one<R>(d, (uint32_t)s, (uint32_t)p, y, vx, vy, vz);
+            b.y[p] = y;
+            b.vx[p] = vx;
+            if (h) {
+                b.vy[p] = vy;
+                b.vz[p] = vz;
+            }
+            hits += h;
+            bad |= !(isfinite(vx) && isfinite(vy) && isfinite(vz));
+            c = cell_of<R>(d, y);
+            d.cell[p] = c;
+        } else {
+            c = d.cell[p];
+        }
+        atomicAdd(&hist[c], 1);
+    }
+    if (kMove) {
+        if (hits) atomicAdd(&blk_hits, hits);
+        if (bad) atomicOr(&blk_bad, 1);
+    }
+    __syncthreads();
+    int* row = d.counts + (size_t)w.y * Cc;
+    for (int c = threadIdx.x; c < Cc; c += blockDim.x) row[c] = hist[c];
+    if (kMove && threadIdx.x == 0) {
+        if (blk_hits) atomicAdd(&d.sc->n_hits, (unsigned long long)blk_hits);
+        if (blk_bad) atomicOr(&d.sc->status, 1);
+    }
+}
+
+// ------------------------------------------------------- column scans
+// The tile histograms form a (tiles x Cc) matrix stored tile-major.  The
+// scatter base of (tile t, cell c) is offset[c] + sum_{t' < t} count[t'][c];
+// it is built column-wise in segments of kSegTiles tiles so that every access
+// is coalesced across consecutive cells.
+__global__ __launch_bounds__(kColThreads) void k_colsum(const InstDesc* __restrict__ descs,
+                                                      const int4* __restrict__ work) {
+    const int4 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int c = w.y * kColThreads + (int)threadIdx.x;
+    if (c >= d.Cc) return;
+    const int t0 = w.z * kSegTiles, t1 = min(t0 + kSegTiles, d.tiles);
+    int sum = 0;
+    for (int t = t0; t < t1; ++t) sum += d.counts[(size_t)t * d.Cc + c];
+    d.segsum[(size_t)w.z * d.Cc + c] = sum;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Per instance: count[c] = column total, offset = exclusive scan of counts in
+// cell order, segment bases = offset + exclusive scan over segments.  Also
+// advances the instance's step counter (and the sampled-step count).
+__global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restrict__ descs,
+                                                     int do_scan) {
+    const InstDesc& d = descs[blockIdx.x];
+    __shared__ int wsum[kScanThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (do_scan) {
+        const int Cc = d.Cc, nseg = d.nseg;
+        const int per = (Cc + kScanThreads - 1) / kScanThreads;
+        const int c0 = min(tid * per, Cc), c1 = min(c0 + per, Cc);
+        int local = 0;
+        for (int c = c0; c < c1; ++c) {
+            int tot = 0;
+            for (int g = 0; g < nseg; ++g) {
+                int* e = d.segsum + (size_t)g * Cc + c;
+                const int v = *e;
+                *e = tot;
+                tot += v;
+            }
+            d.count[c] = tot;
+            local += tot;
+        }
+        const int incl = wave_incl_scan(local, lane);
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        if (wv == 0) {
+            int v = lane < kScanThreads / 64 ? wsum[lane] : 0;
+            v = wave_incl_scan(v, lane);
+            if (lane < kScanThreads / 64) wsum[lane] = v;
+        }
+        __syncthreads();
+        int run = incl - local + (wv ? wsum[wv - 1] : 0);
+        for (int c = c0; c < c1; ++c) {
+            d.offset[c] = run;
+            const int base = run;
+            run += d.count[c];
+            for (int g = 0; g < nseg; ++g) d.segsum[(size_t)g * Cc + c] += base;
+        }
+        if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != d.N) atomicOr(&d.sc->status, 2);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int64_t s = d.sc->step_done + 1;
+        d.sc->step_done = s;
+        if ((d.phase_mask & kPhaseSample) && s > d.n_transient) d.sc->n_sampled += 1;
+    }
+}
+
+__global__ __launch_bounds__(kColThreads) void k_colprefix(const InstDesc* __restrict__ descs,
+                                                         const int4* __restrict__ work) {
+    const int4 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int c = w.y * kColThreads + (int)threadIdx.x;
+    if (c >= d.Cc) return;
+    const int t0 = w.z * kSegTiles, t1 = min(t0 + kSegTiles, d.tiles);
+    int run = d.segsum[(size_t)w.z * d.Cc + c];
+    for (int t = t0; t < t1; ++t) {
+        int* e = d.counts + (size_t)t * d.Cc + c;
+        const int v = *e;
+        *e = run;
+        run += v;
+    }
+}
+
+// --------------------------------------------------------------- scatter
+// Stable scatter of one tile.  The tile is walked in rounds of 256 slots in
+// slot order; within a wavefront, equal cells are grouped with ballots (the
+// rank of a slot is the number of lower lanes with the same cell); across the
+// four wavefronts of a round, each wavefront's (cell, count) list is shared in
+// LDS; per-cell running bases live in LDS.  The destination of every slot is
+// therefore base + (number of earlier slots of the tile with the same cell),
+// exactly a stable counting sort.
+template <class R>
+__global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __restrict__ descs,
+                                                             const int2* __restrict__ work) {
+    extern __shared__ int running[];
+    __shared__ int wl_cell[kParticleThreads / 64][64];
+    __shared__ int wl_cnt[kParticleThreads / 64][64];
+    __shared__ int wl_n[kParticleThreads / 64];
+    const int2 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int Cc = d.Cc;
+    const int* brow = d.counts + (size_t)w.y * Cc;
+    for (int c = threadIdx.x; c < Cc; c += blockDim.x) running[c] = brow[c];
+    const int64_t s = d.sc->step_done;
+    const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
+    const P4<R> dst = particles<R>(d, (int)(s & 1));
+    const int start = w.y * d.tile_items;
+    const int end = min(start + d.tile_items, d.N);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long lt = lanes_below(lane);
+    __syncthreads();
+    for (int base = start; base < end; base += kParticleThreads) {
+        const int i = base + (int)threadIdx.x;
+        const bool valid = i < end;
+        int c = -1;
+        R ry = R(0), rvx = R(0), rvy = R(0), rvz = R(0);
+        if (valid) {
+            c = d.cell[i];
+            ry = src.y[i];
+            rvx = src.vx[i];
+            rvy = src.vy[i];
+            rvz = src.vz[i];
+        }
+        unsigned long long remaining = __ballot(valid);
+        unsigned long long mine = 0;
+        int ng = 0;
+        while (remaining) {
+            const int leader = __builtin_ctzll(remaining);
+            const int lc = __shfl(c, leader, 64);
+            const unsigned long long m = __ballot(c == lc);
+            if (c == lc) mine = m;
+            if (lane == leader) {
+                wl_cell[wv][ng] = lc;
+                wl_cnt[wv][ng] = __popcll(m);
+            }
+            ++ng;
+            remaining &= ~m;
+        }
+        if (lane == 0) wl_n[wv] = ng;
+        __syncthreads();
+        int pos = 0;
+        if (valid) {
+            pos = running[c] + __popcll(mine & lt);
+            for (int w2 = 0; w2 < wv; ++w2) {
+                const int n2 = wl_n[w2];
+                for (int g2 = 0; g2 < n2; ++g2) {
+                    if (wl_cell[w2][g2] == c) {
+                        pos += wl_cnt[w2][g2];
+                        break;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (valid) {
+            if ((mine & lt) == 0) atomicAdd(&running[c], __popcll(mine));
+            dst.y[pos] = ry;
+            dst.vx[pos] = rvx;
+            dst.vy[pos] = rvy;
+            dst.vz[pos] = rvz;
+        }
+    }
+}
+
+// Debug path without sorting: the next buffer is a copy of the current one.
+template <class R>
+__global__ __launch_bounds__(kParticleThreads) void k_copy(const InstDesc* __restrict__ descs,
+                                                          const int2* __restrict__ work) {
+    const int2 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int64_t s = d.sc->step_done;
+    const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
+    const P4<R> dst = particles<R>(d, (int)(s & 1));
+    const int start = w.y * d.tile_items;
+    const int end = min(start + d.tile_items, d.N);
+    for (int p = start + (int)threadIdx.x; p < end; p += blockDim.x) {
+        dst.y[p] = src.y[p];
+        dst.vx[p] = src.vx[p];
+        dst.vy[p] = src.vy[p];
+        dst.vz[p] = src.vz[p];
+    }
+}
+
+// ----------------------------------------------------- sampling helpers
+struct Mom {
+    double s[kMoments];
+};
+
+__device__ __forceinline__ void mom_zero(Mom& m) {
+#pragma unroll
+    for (int k = 0; k < kMoments; ++k) m.s[k] = 0.0;
+}
+
+__device__ __forceinline__ void mom_add(Mom& m, double x, double y, double z) {
+    const double v2 = (x * x + y * y) + z * z;
+    m.s[0] += 1.0;
+    m.s[1] += x;
+    m.s[2] += y;
+    m.s[3] += z;
+    m.s[4] += x * x;
+    m.s[5] += y * y;
+    m.s[6] += z * z;
+    m.s[7] += x * y;
+    m.s[8] += x * z;
+    m.s[9] += y * z;
+    m.s[10] += v2 * x;
+    m.s[11] += v2 * y;
+}
+
+// ------------------------------------------------ collide (deterministic)
+// NTC (Bird) per collision cell, one lane per cell and 64 cells per
+// wavefront: M_real = N(N-1)/2 crmax K + rem candidates; each candidate draws
+// a distinct uniform pair, raises crmax to its relative speed if larger, is
+// accepted with probability c_r / crmax (hard spheres) and then scatters
+// isotropically about the centre of mass.  Candidates run in order, so the
+// result is the reference recipe's to the last bit.  The sampling step's
+// twelve FP64 sums of the cell follow in slot order.
+__global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__ descs,
+                                                   const int4* __restrict__ work, int do_collide) {
+    const int4 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int c = w.y + (int)threadIdx.x;
+    const int64_t s = d.sc->step_done;
+    const bool sample = (d.phase_mask & kPhaseSample) && s > d.n_transient;
+    unsigned long long ncoll = 0;
+    if (c < w.z) {
+        const P4<double> b = particles<double>(d, (int)(s & 1));
+        const int n = d.count[c], o = d.offset[c];
+        double* vx = b.vx + o;
+        double* vy = b.vy + o;
+        double* vz = b.vz + o;
+        if (do_collide && n >= 2) {
+            double crm = d.crmax[c];
+            const double mreal = (((0.5 * (double)n) * (double)(n - 1)) * crm) * d.kntc + d.rem[c];
+            const double mf = floor(mreal);
+            d.rem[c] = mreal - mf;
+            const int64_t M = (int64_t)mf;
+            for (int64_t k = 0; k < M; ++k) {
+                Stream st(d.key0, d.key1, (uint32_t)s, (uint32_t)c, (uint32_t)k, kTagColl);
+                double ua, ub;
+                Num<double>::uni2(st.next(), ua, ub);
+                int i = (int)(ua * (double)n);
+                if (i > n - 1) i = n - 1;
+                int j = (int)(ub * (double)(n - 1));
+                if (j > n - 2) j = n - 2;
+                if (j >= i) ++j;
+                const double crx = vx[i] - vx[j];
+                const double cry = vy[i] - vy[j];
+                const double crz = vz[i] - vz[j];
+                const double cr = __builtin_sqrt((crx * crx + cry * cry) + crz * crz);
+                if (cr > crm) crm = cr;
+                double ua2, ub2;
+                Num<double>::uni2(st.next(), ua2, ub2);
+                if (ua2 * crm < cr) {
+                    double dx, dy, dz;
+                    sphere_point<double>(st, dx, dy, dz);
+                    const double cmx = 0.5 * (vx[i] + vx[j]);
+                    const double cmy = 0.5 * (vy[i] + vy[j]);
+                    const double cmz = 0.5 * (vz[i] + vz[j]);
+                    const double hh = 0.5 * cr;
+                    vx[i] = cmx + hh * dx;
+                    vy[i] = cmy + hh * dy;
+                    vz[i] = cmz + hh * dz;
+                    vx[j] = cmx - hh * dx;
+                    vy[j] = cmy - hh * dy;
+                    vz[j] = cmz - hh * dz;
+                    ++ncoll;
+                }
+            }
+            d.crmax[c] = crm;
+        }
+        if (sample) {
+            Mom m;
+            mom_zero(m);
+            for (int q = 0; q < n; ++q) mom_add(m, vx[q], vy[q], vz[q]);
+            double* a = d.acc + (size_t)c * kMoments;
+#pragma unroll
+            for (int k = 0; k < kMoments; ++k) a[k] += m.s[k];
+        }
+    }
+    if (ncoll) atomicAdd(&d.sc->n_coll, ncoll);
+}
+
+// ------------------------------------------------------- collide (fast)
+// The same NTC candidates (pair and acceptance drawn per candidate from the
+// cell's counter-based stream) processed 64 at a time by one wavefront per
+// collision cell, on velocities staged in LDS.  Candidates that share a
+// particle with a lower-numbered pending candidate wait for a later round
+// (claims by atomicMin in a per-wavefront LDS table), so every executed
+// candidate sees exactly the velocities of some sequential order: NTC in
+// distribution.  The acceptance test of a candidate uses
+// max(crmax at cell start, its own c_r); crmax is raised at the end of the
+// cell.  Results depend only on the cell's data and stream, not on which
+// workgroup or group the cell runs in.
+template <class R> struct Cand;
+template <> struct Cand<float> {
+    __device__ __forceinline__ static void draw(Stream& st, float& a, float& b, float& c) {
+        const uint4 x = st.next();
+        a = u24(x.x);
+        b = u24(x.y);
+        c = u24(x.z);
+    }
+};
+template <> struct Cand<double> {
+    __device__ __forceinline__ static void draw(Stream& st, double& a, double& b, double& c) {
+        const uint4 x = st.next();
+        a = u53(x.x, x.y);
+        b = u53(x.z, x.w);
+        const uint4 y = st.next();
+        c = u53(y.x, y.y);
+    }
+};
+
+__device__ __forceinline__ double wave_sum_fixed(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <class R>
+__global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc* __restrict__ descs,
+                                                                 const int4* __restrict__ work,
+                                                                 int cap, int do_collide) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nw = blockDim.x >> 6;
+    uint32_t* claims = (uint32_t*)smem;
+    R* lds_v = (R*)(claims + nw * kClaimTable);
+    const int4 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int c0 = w.y, c1 = w.z;
+    const int64_t s = d.sc->step_done;
+    const bool sample = (d.phase_mask & kPhaseSample) && s > d.n_transient;
+    const P4<R> g = particles<R>(d, (int)(s & 1));
+    const int s0 = d.offset[c0];
+    const int n = d.offset[c1 - 1] + d.count[c1 - 1] - s0;
+    const bool staged = n <= cap;
+    R *vx, *vy, *vz;
+    if (staged) {
+        vx = lds_v;
+        vy = lds_v + cap;
+        vz = lds_v + 2 * cap;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            vx[i] = g.vx[s0 + i];
+            vy[i] = g.vy[s0 + i];
+            vz[i] = g.vz[s0 + i];
+        }
+    } else {
+        vx = g.vx + s0;
+        vy = g.vy + s0;
+        vz = g.vz + s0;
+    }
+    for (int i = threadIdx.x; i < nw * kClaimTable; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long lt = lanes_below(lane);
+    uint32_t* tab = claims + wv * kClaimTable;
+    unsigned long long ncoll = 0;
+    for (int c = c0 + wv; c < c1; c += nw) {
+        const int nc = d.count[c];
+        const int o = d.offset[c] - s0;
+        if (do_collide && nc >= 2) {
+            const double crm0 = d.crmax[c];
+            const double mreal = (((0.5 * (double)nc) * (double)(nc - 1)) * crm0) * d.kntc + d.rem[c];
+            const double mf = floor(mreal);
+            if (lane == 0) d.rem[c] = mreal - mf;
+            const int64_t M = (int64_t)mf;
+            const R crmr = (R)crm0;
+            R lane_max = R(0);
+            int64_t next = 0;
+            int64_t myk = -1;
+            int mi = 0, mj = 0;
+            R macc = R(0);
+            Stream st(d.key0, d.key1, (uint32_t)s, (uint32_t)c, 0u, kTagColl);
+            for (;;) {
+                const bool idle = myk < 0;
+                const unsigned long long idle_mask = __ballot(idle);
+                if (idle) {
+                    const int64_t k = next + __popcll(idle_mask & lt);
+                    if (k < M) {
+                        myk = k;
+                        st = Stream(d.key0, d.key1, (uint32_t)s, (uint32_t)c, (uint32_t)k, kTagColl);
+                        R ua, ub;
+                        Cand<R>::draw(st, ua, ub, macc);
+                        mi = min((int)(ua * (R)nc), nc - 1);
+                        mj = min((int)(ub * (R)(nc - 1)), nc - 2);
+                        if (mj >= mi) ++mj;
+                    }
+                }
+                next += __popcll(idle_mask);
+                const bool active = myk >= 0;
+                if (__ballot(active) == 0ull) break;
+                const int hi = mi & (kClaimTable - 1), hj = mj & (kClaimTable - 1);
+                if (active) {
+                    atomicMin(&tab[hi], (uint32_t)myk);
+                    atomicMin(&tab[hj], (uint32_t)myk);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const bool win = active && tab[hi] == (uint32_t)myk && tab[hj] == (uint32_t)myk;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                if (active) {
+                    tab[hi] = 0xFFFFFFFFu;
+                    tab[hj] = 0xFFFFFFFFu;
+                }
+                if (win) {
+                    const int i = o + mi, j = o + mj;
+                    const R xi = vx[i], yi = vy[i], zi = vz[i];
+                    const R xj = vx[j], yj = vy[j], zj = vz[j];
+                    const R crx = xi - xj, cry = yi - yj, crz = zi - zj;
+                    const R cr = Num<R>::sqrt((crx * crx + cry * cry) + crz * crz);
+                    lane_max = cr > lane_max ? cr : lane_max;
+                    const R cm = cr > crmr ? cr : crmr;
+                    if (macc * cm < cr) {
+                        R dx, dy, dz;
+                        sphere_point<R>(st, dx, dy, dz);
+                        const R cmx = R(0.5) * (xi + xj), cmy = R(0.5) * (yi + yj),
+                                cmz = R(0.5) * (zi + zj);
+                        const R hh = R(0.5) * cr;
+                        vx[i] = cmx + hh * dx;
+                        vy[i] = cmy + hh * dy;
+                        vz[i] = cmz + hh * dz;
+                        vx[j] = cmx - hh * dx;
+                        vy[j] = cmy - hh * dy;
+                        vz[j] = cmz - hh * dz;
+                        ++ncoll;
+                    }
+                    myk = -1;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            double mx = (double)lane_max;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double other = __shfl_xor(mx, off, 64);
+                mx = other > mx ? other : mx;
+            }
+            if (lane == 0 && mx > crm0) d.crmax[c] = mx;
+        }
+        if (sample) {
+            Mom m;
+            mom_zero(m);
+            for (int q = lane; q < nc; q += 64)
+                mom_add(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
+            double tot[kMoments];
+#pragma unroll
+            for (int k = 0; k < kMoments; ++k) tot[k] = wave_sum_fixed(m.s[k]);
+            if (lane == 0) {
+                double* a = d.acc + (size_t)c * kMoments;
+#pragma unroll
+                for (int k = 0; k < kMoments; ++k) a[k] += tot[k];
+            }
+        }
+    }
+    __syncthreads();
+    if (staged && do_collide) {
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            g.vx[s0 + i] = vx[i];
+            g.vy[s0 + i] = vy[i];
+            g.vz[s0 + i] = vz[i];
+        }
+    }
+    if (ncoll) atomicAdd(&d.sc->n_coll, ncoll);
+}
+
+// ----------------------------------------------------------- estimators
+// Per sampling cell (its collision cells summed in order) with K sampled
+// steps and N particles: density nu = S0 C/(K N); u = S1/S0;
+// M_ab = S2_ab/S0 - u_a u_b; T = trace(M)/3; P_xy = nu M_xy;
+// <|c|^2 c_a> from the raw moments; q_a = nu <|c|^2 c_a>/2; mass flow
+// Q = sum S1_x/(K N).  Velocities, heat fluxes and Q are divided by
+// v0 = sqrt(2) and stresses are over n kT: the dimensionless variables of
+// Eq. 6.
+__global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ descs) {
+    const InstDesc& d = descs[blockIdx.x];
+    const int C = d.C, ns = d.n_sub;
+    const double K = (double)d.sc->n_sampled, N = (double)d.N;
+    const double v0 = __builtin_sqrt(2.0);
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        double s[kMoments];
+        for (int m = 0; m < kMoments; ++m) s[m] = 0.0;
+        for (int k = 0; k < ns; ++k) {
+            const double* a = d.acc + ((size_t)c * ns + k) * kMoments;
+            for (int m = 0; m < kMoments; ++m) s[m] += a[m];
+        }
+        const double n_c = (s[0] * (double)C) / (K * N);
+        const double u = s[1] / s[0], v = s[2] / s[0], ww = s[3] / s[0];
+        const double mxx = s[4] / s[0] - u * u;
+        const double myy = s[5] / s[0] - v * v;
+        const double mzz = s[6] / s[0] - ww * ww;
+        const double mxy = s[7] / s[0] - u * v;
+        const double trace2 = (s[4] + s[5]) + s[6];
+        const double usq = (u * u + v * v) + ww * ww;
+        const double cx = ((s[10] / s[0] - u * (trace2 / s[0])) -
+                           2.0 * (((u * s[4] + v * s[7]) + ww * s[8]) / s[0])) + 2.0 * u * usq;
+        const double cy = ((s[11] / s[0] - v * (trace2 / s[0])) -
+                           2.0 * (((u * s[7] + v * s[5]) + ww * s[9]) / s[0])) + 2.0 * v * usq;
+        double* e = d.est;
+        e[0 * C + c] = n_c;
+        e[1 * C + c] = u / v0;
+        e[2 * C + c] = v / v0;
+        e[3 * C + c] = ww / v0;
+        e[4 * C + c] = ((mxx + myy) + mzz) / 3.0;
+        e[5 * C + c] = n_c * mxy;
+        e[6 * C + c] = (0.5 * n_c * cx) / v0;
+        e[7 * C + c] = (0.5 * n_c * cy) / v0;
+    }
+    if (threadIdx.x == 0) {
+        double q = 0.0;
+        for (int c = 0; c < C; ++c) {
+            double sx = 0.0;
+            for (int k = 0; k < ns; ++k) sx += d.acc[((size_t)c * ns + k) * kMoments + 1];
+            q += sx;
+        }
+        d.est[kEstPerCell * C] = (q / (K * N)) / v0;
+        d.est[kEstPerCell * C + 1] = K;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reset_window(const InstDesc* __restrict__ descs) {
+    const InstDesc& d = descs[blockIdx.x];
+    const size_t n = (size_t)d.Cc * kMoments;
+    for (size_t i = threadIdx.x; i < n; i += blockDim.x) d.acc[i] = 0.0;
+    if (threadIdx.x == 0) {
+        d.sc->n_sampled = 0;
+        d.sc->n_coll = 0;
+    }
+}
+
+template <class R>
+void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipEvent_t* ev = nullptr) {
+    const size_t hist_lds = (size_t)w.max_cc * sizeof(int);
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    if (phase & (kPhaseMove | kPhaseSort)) {
+        if (phase & kPhaseMove)
+            hipLaunchKernelGGL((k_move_hist<R, true>), dim3(w.n_tiles), dim3(kParticleThreads),
+                               hist_lds, st, w.desc, w.tiles);
+        else
+            hipLaunchKernelGGL((k_move_hist<R, false>), dim3(w.n_tiles), dim3(kParticleThreads),
+                               hist_lds, st, w.desc, w.tiles);
+    }
+    mark(1);
+    if (phase & kPhaseSort) {
+        hipLaunchKernelGGL(k_colsum, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
+        mark(2);
+        hipLaunchKernelGGL(k_scan, dim3(w.n_inst), dim3(kScanThreads), 0, st, w.desc, 1);
+        mark(3);
+        hipLaunchKernelGGL(k_colprefix, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
+        mark(4);
+        hipLaunchKernelGGL((k_scatter<R>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds, st,
+                           w.desc, w.tiles);
+    } else {
+        mark(2);
+        hipLaunchKernelGGL(k_scan, dim3(w.n_inst), dim3(kScanThreads), 0, st, w.desc, 0);
+        mark(3);
+        mark(4);
+        hipLaunchKernelGGL((k_copy<R>), dim3(w.n_tiles), dim3(kParticleThreads), 0, st, w.desc,
+                           w.tiles);
+    }
+    mark(5);
+    if (phase & (kPhaseCollide | kPhaseSample)) {
+        const int do_collide = (phase & kPhaseCollide) ? 1 : 0;
+        if (mode == kFp64Det) {
+            hipLaunchKernelGGL(k_collide_det, dim3(w.n_cblocks), dim3(64), 0, st, w.desc, w.cblocks,
+                               do_collide);
+        } else {
+            hipLaunchKernelGGL((k_collide_fast<R>), dim3(w.n_cblocks), dim3(64 * kFastWaves),
+                               fast_collide_lds_bytes(mode, w.fast_cap), st, w.desc, w.cblocks,
+                               w.fast_cap, do_collide);
+        }
+    }
+    mark(6);
+}
+
+}  // namespace
+
+size_t fast_collide_lds_bytes(Mode mode, int cap) {
+    const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
+    return (size_t)kFastWaves * kClaimTable * sizeof(uint32_t) + 3 * (size_t)cap * rb;
+}
+
+void launch_init(const InstDesc& d, const InstDesc* d_desc, Mode mode, hipStream_t s) {
+    const int n = d.N > d.Cc ? d.N : d.Cc;
+    const dim3 grid((n + 255) / 256);
+    if (mode == kFp32Fast)
+        hipLaunchKernelGGL(k_init<float>, grid, dim3(256), 0, s, d_desc);
+    else
+        hipLaunchKernelGGL(k_init<double>, grid, dim3(256), 0, s, d_desc);
+}
+
+void launch_step(const Work& w, Mode mode, unsigned phase, hipStream_t s) {
+    if (mode == kFp32Fast)
+        step_kernels<float>(w, mode, phase, s);
+    else
+        step_kernels<double>(w, mode, phase, s);
+}
+
+hipError_t configure_kernels(size_t max_dynamic_lds) {
+    const int bytes = (int)max_dynamic_lds;
+    hipError_t e = hipSuccess;
+    auto set = [&](const void* f) {
+        const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (r != hipSuccess) e = r;
+    };
+    set((const void*)k_collide_fast<float>);
+    set((const void*)k_collide_fast<double>);
+    set((const void*)k_move_hist<float, true>);
+    set((const void*)k_move_hist<float, false>);
+    set((const void*)k_move_hist<double, true>);
+    set((const void*)k_move_hist<double, false>);
+    set((const void*)k_scatter<float>);
+    set((const void*)k_scatter<double>);
+    return e;
+}
+
+void launch_step_timed(const Work& w, Mode mode, unsigned phase, hipStream_t s, hipEvent_t* ev) {
+    if (mode == kFp32Fast)
+        step_kernels<float>(w, mode, phase, s, ev);
+    else
+        step_kernels<double>(w, mode, phase, s, ev);
+}
+
+void launch_finalize(const InstDesc* d_desc, int n_inst, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(256), 0, s, d_desc);
+}
+
+void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_window, dim3(n_inst), dim3(256), 0, s, d_desc);
+}
+
+}  // namespace dsmc

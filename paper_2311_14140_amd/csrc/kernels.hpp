@@ -1,0 +1,37 @@
+// kernels.hpp -- host-side launchers of the DSMC kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.hpp"
+
+namespace dsmc {
+
+enum Mode : int { kFp64Det = 0, kFp32Fast = 1, kFp64Fast = 2 };
+
+// Work lists built by the runtime for a group of instances.
+struct Work {
+    const InstDesc* desc;   // device array, one per instance
+    int n_inst;
+    const int2* tiles;      // (instance, tile) for the particle kernels
+    int n_tiles;
+    const int4* cols;       // (instance, cell chunk, segment) for the column scans
+    int n_cols;
+    const int4* cblocks;    // (instance, first cell, end cell) collide blocks
+    int n_cblocks;
+    int max_cc;             // largest collision-cell count (LDS of histograms)
+    int fast_cap;           // particles a fast-collide workgroup stages in LDS
+};
+
+void launch_init(const InstDesc& d, const InstDesc* d_desc, Mode mode, hipStream_t s);
+// One step of every instance in the group; phase is a DSMC_PHASE_* mask.
+void launch_step(const Work& w, Mode mode, unsigned phase, hipStream_t s);
+// The same step with an event recorded before each of its kernels and one
+// after the last (ev must hold 7 events); the kernel order is the one of
+// dsmc_profile_step.
+void launch_step_timed(const Work& w, Mode mode, unsigned phase, hipStream_t s, hipEvent_t* ev);
+void launch_finalize(const InstDesc* d_desc, int n_inst, hipStream_t s);
+void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s);
+size_t fast_collide_lds_bytes(Mode mode, int cap);
+// Allow dynamic LDS up to max_dynamic_lds bytes for the kernels that use it.
+hipError_t configure_kernels(size_t max_dynamic_lds);
+
+}  // namespace dsmc

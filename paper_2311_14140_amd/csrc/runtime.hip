@@ -1,0 +1,805 @@
+// runtime.hip -- host runtime behind the C ABI in include/dsmc.h: parameter
+// checks, the per-instance device arena, work lists and launch shapes of a
+// group, step enqueueing and HIP-graph replay, estimator read-back, state
+// export and import, and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "dsmc.h"
+#include "kernels.hpp"
+
+using namespace dsmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(std::string* sink, int code, const std::string& msg) {
+    if (sink) *sink = msg;
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(sink, expr)                                                           \
+    do {                                                                              \
+        const hipError_t e_ = (expr);                                                 \
+        if (e_ != hipSuccess)                                                         \
+            return fail(sink, DSMC_ERR_DEVICE,                                        \
+                        std::string(#expr ": ") + hipGetErrorString(e_));             \
+    } while (0)
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Derived sizes and constants of one instance (the same for footprint and
+// creation).  Constants are evaluated once each, in double, in the order
+// written, so they equal the reference recipe's.
+struct Plan {
+    int mode = 0;
+    size_t rb = 8;  // bytes per real
+    int32_t N = 0, C = 0, Cc = 0, ns = 1, ppc = 0;
+    int32_t tile_items = 256, tiles = 1, nseg = 1;
+    double H = 1.0, lam = 0, dt = 0, g = 0, kntc = 0, crmax0 = 0, sqrt_tw = 1, inv_dy = 0;
+    // arena offsets
+    uint64_t off_buf[2][4], off_cell, off_counts, off_segsum, off_count, off_offset, off_crmax,
+        off_rem, off_acc, off_est, off_sc, off_desc, total;
+};
+
+int base_items_per_thread(int32_t N, int32_t Cc) {
+    // Tiles of 256 * k slots with at least 4 slots per collision cell keep the
+    // per-tile histogram traffic near one byte per particle.
+    int k = (int)std::ceil(4.0 * (double)Cc / (double)kParticleThreads);
+    k = std::max(1, std::min(64, k));
+    const int64_t need = (int64_t)((N + kParticleThreads - 1) / kParticleThreads);
+    if (need < k) k = (int)std::max<int64_t>(1, need);
+    return k;
+}
+
+int check_params(const dsmc_params* p, std::string* err) {
+    if (!p) return fail(err, DSMC_ERR_INVALID_ARG, "params is NULL");
+    if (p->struct_size != sizeof(dsmc_params))
+        return fail(err, DSMC_ERR_INVALID_ARG, "params.struct_size != sizeof(dsmc_params)");
+    if (p->precision != DSMC_FP64_DETERMINISTIC && p->precision != DSMC_FP32_FAST &&
+        p->precision != DSMC_FP64_FAST)
+        return fail(err, DSMC_ERR_INVALID_ARG, "unknown precision");
+    if (!(std::isfinite(p->kn) && p->kn > 0.0)) return fail(err, DSMC_ERR_INVALID_ARG, "kn must be finite and > 0");
+    if (!std::isfinite(p->body_force)) return fail(err, DSMC_ERR_INVALID_ARG, "body_force must be finite");
+    if (!(std::isfinite(p->wall_temperature) && p->wall_temperature > 0.0))
+        return fail(err, DSMC_ERR_INVALID_ARG, "wall_temperature must be finite and > 0");
+    if (!std::isfinite(p->dt)) return fail(err, DSMC_ERR_INVALID_ARG, "dt must be finite");
+    if (p->n_cells < 1 || p->particles_per_cell < 1 || p->n_sub < 1)
+        return fail(err, DSMC_ERR_INVALID_ARG, "n_cells, particles_per_cell and n_sub must be >= 1");
+    if ((int64_t)p->n_cells * p->particles_per_cell > (int64_t)INT32_MAX / 2)
+        return fail(err, DSMC_ERR_INVALID_ARG, "too many particles for int32 slots");
+    if ((int64_t)p->n_cells * p->n_sub > 65536)
+        return fail(err, DSMC_ERR_INVALID_ARG, "n_cells * n_sub exceeds 65536 collision cells");
+    if (p->n_transient < 0) return fail(err, DSMC_ERR_INVALID_ARG, "n_transient must be >= 0");
+    if (p->debug_phase_mask > DSMC_PHASE_ALL) return fail(err, DSMC_ERR_INVALID_ARG, "bad phase mask");
+    return DSMC_OK;
+}
+
+Plan make_plan(const dsmc_params* p) {
+    Plan q;
+    q.mode = p->precision;
+    q.rb = p->precision == DSMC_FP32_FAST ? 4 : 8;
+    q.C = p->n_cells;
+    q.ns = p->n_sub;
+    q.Cc = p->n_cells * p->n_sub;
+    q.ppc = p->particles_per_cell;
+    q.N = p->n_cells * p->particles_per_cell;
+    q.H = 1.0;
+    q.lam = p->kn * q.H;
+    if (p->dt > 0.0) {
+        q.dt = p->dt;
+    } else {
+        const double lref = q.lam < q.H ? q.lam : q.H;
+        q.dt = (0.2 * lref) / std::sqrt(2.0);
+    }
+    q.g = 2.0 * p->body_force;
+    q.kntc = (q.dt * (double)p->n_sub) / ((std::sqrt(2.0) * q.lam) * (double)p->particles_per_cell);
+    q.crmax0 = 5.0 * std::sqrt(2.0 * p->wall_temperature);
+    q.sqrt_tw = std::sqrt(p->wall_temperature);
+    q.inv_dy = (double)q.Cc / q.H;
+    const int k = base_items_per_thread(q.N, q.Cc);
+    q.tile_items = k * kParticleThreads;
+    q.tiles = (q.N + q.tile_items - 1) / q.tile_items;
+    q.nseg = (q.tiles + kSegTiles - 1) / kSegTiles;
+
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 4; ++a) q.off_buf[b][a] = take((uint64_t)q.N * q.rb);
+    q.off_cell = take((uint64_t)q.N * 4);
+    q.off_counts = take((uint64_t)q.tiles * q.Cc * 4);
+    q.off_segsum = take((uint64_t)q.nseg * q.Cc * 4);
+    q.off_count = take((uint64_t)q.Cc * 4);
+    q.off_offset = take((uint64_t)q.Cc * 4);
+    q.off_crmax = take((uint64_t)q.Cc * 8);
+    q.off_rem = take((uint64_t)q.Cc * 8);
+    q.off_acc = take((uint64_t)q.Cc * kMoments * 8);
+    q.off_est = take(((uint64_t)kEstPerCell * q.C + 2) * 8);
+    q.off_sc = take(sizeof(DevScalars));
+    q.off_desc = take(sizeof(InstDesc));
+    q.total = o + kAlign;  // slack to align an unaligned arena
+    return q;
+}
+
+int device_max_lds() {
+    static int cached = -1;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cached < 0) {
+        // Largest dynamic LDS a workgroup may use: the device's per-block limit
+        // if the kernels accept it, else 64 KiB.  Errors of the probing calls
+        // are cleared so they do not surface at a later launch.
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        (void)hipGetLastError();
+        cached = 65536;
+        hipError_t e1 = hipSuccess, e2 = hipSuccess;
+        if (v > 65536) {
+            e1 = dsmc::configure_kernels((size_t)v);
+            if (e1 == hipSuccess) cached = v;
+            (void)hipGetLastError();
+        }
+        if (cached == 65536) {
+            e2 = dsmc::configure_kernels((size_t)cached);
+            (void)hipGetLastError();
+        }
+        if (std::getenv("DSMC_VERBOSE"))
+            std::fprintf(stderr, "dsmc: device max LDS per block %d, using %d (%s / %s)\n", v, cached,
+                         hipGetErrorString(e1), hipGetErrorString(e2));
+    }
+    return cached;
+}
+
+}  // namespace
+
+struct dsmc_group;
+
+struct dsmc_handle {
+    dsmc_params p{};
+    Plan plan;
+    InstDesc desc{};          // host copy; desc.buf etc. point into the arena
+    InstDesc* d_desc = nullptr;  // device copy of desc (init, sample, reset)
+    void* mem = nullptr;
+    bool owns_mem = false;
+    hipStream_t stream = nullptr;
+    dsmc_group* group = nullptr;  // user group
+    dsmc_group* solo = nullptr;   // private group behind dsmc_step
+    // true once a sort has run since the last dsmc_set_state: the device cell
+    // array then holds pre-sort cells and the current slot order's cells
+    // follow from the counts and offsets
+    bool sorted = false;
+    std::string err;
+};
+
+struct dsmc_group {
+    hipStream_t stream = nullptr;
+    int mode = -1;
+    bool solo = false;
+    std::vector<dsmc_handle*> members;
+    bool dirty = true;
+    int tile_mult = 0;   // 0 = automatic
+    int cpb = 0;         // 0 = automatic
+    // device-side work lists
+    void* d_mem = nullptr;
+    size_t d_bytes = 0;
+    Work work{};
+    unsigned phase = DSMC_PHASE_ALL;
+    // graph of kGraphSteps steps
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::string err;
+};
+
+namespace {
+
+constexpr int kGraphSteps = 8;
+
+hipStream_t stream_of(const dsmc_handle* h) {
+    return h->group ? h->group->stream : h->stream;
+}
+
+void drop_graph(dsmc_group* g) {
+    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->gexec = nullptr;
+    g->graph = nullptr;
+}
+
+int auto_cpb(const dsmc_handle* h) {
+    // Aim at about 2048 particles per fast-collide workgroup, at least one cell.
+    const double per_cell = (double)h->plan.N / (double)h->plan.Cc;
+    int c = (int)std::floor(2048.0 / std::max(per_cell, 1.0));
+    return std::max(1, std::min(c, 64));
+}
+
+// (Re)build the device work lists and launch shapes of a group.
+int rebuild(dsmc_group* g) {
+    drop_graph(g);
+    const int n = (int)g->members.size();
+    std::vector<InstDesc> descs(n);
+    std::vector<int2> tiles;
+    std::vector<int4> cols, cblocks;
+    int max_cc = 1;
+    int cap = 64;
+    for (int i = 0; i < n; ++i) {
+        dsmc_handle* h = g->members[i];
+        InstDesc d = h->desc;
+        if (!g->solo) d.phase_mask = DSMC_PHASE_ALL;
+        // launch shape: tiles may only grow (the histogram matrix is sized
+        // for the base tile)
+        const int mult = g->tile_mult > 0 ? g->tile_mult : 1;
+        const int64_t items = std::min<int64_t>((int64_t)h->plan.tile_items * mult,
+                                                (int64_t)std::max(h->plan.N, 1) + kParticleThreads);
+        d.tile_items = (int32_t)((items + kParticleThreads - 1) / kParticleThreads * kParticleThreads);
+        d.tiles = (d.N + d.tile_items - 1) / d.tile_items;
+        d.nseg = (d.tiles + kSegTiles - 1) / kSegTiles;
+        descs[i] = d;
+        for (int t = 0; t < d.tiles; ++t) tiles.push_back(make_int2(i, t));
+        for (int ch = 0; ch < (d.Cc + kColThreads - 1) / kColThreads; ++ch)
+            for (int sgi = 0; sgi < d.nseg; ++sgi) cols.push_back(make_int4(i, ch, sgi, 0));
+        max_cc = std::max(max_cc, d.Cc);
+        if (g->mode == kFp64Det) {
+            for (int c = 0; c < d.Cc; c += 64) cblocks.push_back(make_int4(i, c, std::min(c + 64, d.Cc), 0));
+        } else {
+            const int cpb = g->cpb > 0 ? g->cpb : auto_cpb(h);
+            for (int c = 0; c < d.Cc; c += cpb) cblocks.push_back(make_int4(i, c, std::min(c + cpb, d.Cc), 0));
+            const double per_cell = (double)d.N / (double)d.Cc;
+            const int want = (int)std::ceil(1.25 * per_cell * cpb + 8.0 * std::sqrt(per_cell * cpb) + 64.0);
+            cap = std::max(cap, want);
+        }
+    }
+    // fit the fast-collide staging area into the device's LDS
+    const size_t rb = g->mode == kFp32Fast ? 4 : 8;
+    const int max_lds = device_max_lds();
+    const size_t fixed = (size_t)kFastWaves * kClaimTable * 4;
+    const int cap_max = (int)(((size_t)max_lds - fixed) / (3 * rb));
+    cap = std::min(cap, cap_max);
+    if ((size_t)max_cc * 4 > (size_t)max_lds)
+        return fail(&g->err, DSMC_ERR_INVALID_ARG, "collision cells exceed the LDS histogram");
+
+    const size_t need = align_up(sizeof(InstDesc) * std::max(n, 1)) + align_up(sizeof(int2) * std::max<size_t>(tiles.size(), 1)) +
+                        align_up(sizeof(int4) * std::max<size_t>(cols.size(), 1)) +
+                        align_up(sizeof(int4) * std::max<size_t>(cblocks.size(), 1));
+    if (need > g->d_bytes) {
+        if (g->d_mem) {
+            (void)hipStreamSynchronize(g->stream);
+            (void)hipFree(g->d_mem);
+        }
+        g->d_mem = nullptr;
+        g->d_bytes = 0;
+        HIP_TRY(&g->err, hipMalloc(&g->d_mem, need));
+        g->d_bytes = need;
+    }
+    char* base = (char*)g->d_mem;
+    size_t o = 0;
+    InstDesc* d_desc = (InstDesc*)(base + o);
+    o += align_up(sizeof(InstDesc) * std::max(n, 1));
+    int2* d_tiles = (int2*)(base + o);
+    o += align_up(sizeof(int2) * std::max<size_t>(tiles.size(), 1));
+    int4* d_cols = (int4*)(base + o);
+    o += align_up(sizeof(int4) * std::max<size_t>(cols.size(), 1));
+    int4* d_cb = (int4*)(base + o);
+    // the stream may still be using the previous lists
+    HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
+    if (n) HIP_TRY(&g->err, hipMemcpy(d_desc, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
+    if (!tiles.empty()) HIP_TRY(&g->err, hipMemcpy(d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice));
+    if (!cols.empty()) HIP_TRY(&g->err, hipMemcpy(d_cols, cols.data(), sizeof(int4) * cols.size(), hipMemcpyHostToDevice));
+    if (!cblocks.empty()) HIP_TRY(&g->err, hipMemcpy(d_cb, cblocks.data(), sizeof(int4) * cblocks.size(), hipMemcpyHostToDevice));
+    g->work.desc = d_desc;
+    g->work.n_inst = n;
+    g->work.tiles = d_tiles;
+    g->work.n_tiles = (int)tiles.size();
+    g->work.cols = d_cols;
+    g->work.n_cols = (int)cols.size();
+    g->work.cblocks = d_cb;
+    g->work.n_cblocks = (int)cblocks.size();
+    g->work.max_cc = max_cc;
+    g->work.fast_cap = cap;
+    g->phase = (g->solo && n == 1 && g->members[0]->p.debug_phase_mask)
+                   ? g->members[0]->p.debug_phase_mask
+                   : (unsigned)DSMC_PHASE_ALL;
+    g->dirty = false;
+    return DSMC_OK;
+}
+
+int enqueue_steps(dsmc_group* g, int64_t n_steps) {
+    if (n_steps < 0) return fail(&g->err, DSMC_ERR_INVALID_ARG, "n_steps < 0");
+    if (g->members.empty() || n_steps == 0) return DSMC_OK;
+    if (g->dirty) {
+        const int r = rebuild(g);
+        if (r) return r;
+    }
+    const Mode mode = (Mode)g->mode;
+    int64_t left = n_steps;
+    if (left >= kGraphSteps && g->phase == DSMC_PHASE_ALL) {
+        if (!g->gexec) {
+            if (!g->cap_stream) HIP_TRY(&g->err, hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+            HIP_TRY(&g->err, hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < kGraphSteps; ++k) launch_step(g->work, mode, g->phase, g->cap_stream);
+            hipGraph_t graph = nullptr;
+            HIP_TRY(&g->err, hipStreamEndCapture(g->cap_stream, &graph));
+            g->graph = graph;
+            HIP_TRY(&g->err, hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0));
+        }
+        while (left >= kGraphSteps) {
+            HIP_TRY(&g->err, hipGraphLaunch(g->gexec, g->stream));
+            left -= kGraphSteps;
+        }
+    }
+    for (int64_t k = 0; k < left; ++k) launch_step(g->work, mode, g->phase, g->stream);
+    HIP_TRY(&g->err, hipGetLastError());
+    return DSMC_OK;
+}
+
+int sync_check(dsmc_handle* h) {
+    HIP_TRY(&h->err, hipStreamSynchronize(stream_of(h)));
+    DevScalars sc;
+    HIP_TRY(&h->err, hipMemcpy(&sc, h->desc.sc, sizeof sc, hipMemcpyDeviceToHost));
+    if (sc.status & 1) return fail(&h->err, DSMC_ERR_NUMERIC, "non-finite particle velocity");
+    if (sc.status & 2) return fail(&h->err, DSMC_ERR_NUMERIC, "cell counts do not add up to N");
+    return DSMC_OK;
+}
+
+int group_init(dsmc_group* g, hipStream_t stream, bool solo) {
+    g->stream = stream;
+    g->solo = solo;
+    return DSMC_OK;
+}
+
+void group_free(dsmc_group* g) {
+    if (!g) return;
+    if (g->stream || !g->members.empty()) (void)hipStreamSynchronize(g->stream);
+    drop_graph(g);
+    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+    if (g->d_mem) (void)hipFree(g->d_mem);
+    delete g;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+const char* dsmc_status_string(int status) {
+    switch (status) {
+        case DSMC_OK: return "ok";
+        case DSMC_ERR_INVALID_ARG: return "invalid argument";
+        case DSMC_ERR_OUT_OF_MEMORY: return "out of memory";
+        case DSMC_ERR_DEVICE: return "device error";
+        case DSMC_ERR_STATE: return "invalid state";
+        case DSMC_ERR_NUMERIC: return "numeric error";
+        default: return "unknown status";
+    }
+}
+
+const char* dsmc_last_error(const dsmc_handle* h) {
+    return h ? h->err.c_str() : g_last_error.c_str();
+}
+
+int dsmc_params_init(dsmc_params* p) {
+    if (!p) return fail(nullptr, DSMC_ERR_INVALID_ARG, "params is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(dsmc_params);
+    p->precision = DSMC_FP64_DETERMINISTIC;
+    p->kn = 1.0;
+    p->body_force = 0.0;
+    p->wall_temperature = 1.0;
+    p->dt = 0.0;
+    p->n_cells = 100;
+    p->particles_per_cell = 50;
+    p->n_sub = 1;
+    p->n_transient = 1000;
+    p->seed = 0;
+    return DSMC_OK;
+}
+
+int dsmc_footprint_bytes(const dsmc_params* p, uint64_t* bytes) {
+    const int r = check_params(p, nullptr);
+    if (r) return r;
+    if (!bytes) return fail(nullptr, DSMC_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = make_plan(p).total;
+    return DSMC_OK;
+}
+
+int dsmc_create(const dsmc_params* p, void* stream, void* arena, uint64_t arena_bytes,
+                dsmc_handle** out) {
+    if (out) *out = nullptr;
+    if (!out) return fail(nullptr, DSMC_ERR_INVALID_ARG, "out is NULL");
+    int r = check_params(p, nullptr);
+    if (r) return r;
+    const Plan q = make_plan(p);
+    if (arena && arena_bytes < q.total) return fail(nullptr, DSMC_ERR_OUT_OF_MEMORY, "arena smaller than dsmc_footprint_bytes");
+    dsmc_handle* h = new (std::nothrow) dsmc_handle();
+    if (!h) return fail(nullptr, DSMC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    h->p = *p;
+    h->plan = q;
+    h->stream = (hipStream_t)stream;
+    if (arena) {
+        h->mem = arena;
+    } else {
+        const hipError_t e = hipMalloc(&h->mem, q.total);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(nullptr, e == hipErrorOutOfMemory ? DSMC_ERR_OUT_OF_MEMORY : DSMC_ERR_DEVICE,
+                        std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        h->owns_mem = true;
+    }
+    char* base = (char*)(((uintptr_t)h->mem + kAlign - 1) / kAlign * kAlign);
+    InstDesc& d = h->desc;
+    d.N = q.N;
+    d.C = q.C;
+    d.Cc = q.Cc;
+    d.n_sub = q.ns;
+    d.tiles = q.tiles;
+    d.tile_items = q.tile_items;
+    d.nseg = q.nseg;
+    d.ppc = q.ppc;
+    d.H = q.H;
+    d.dt = q.dt;
+    d.g = q.g;
+    d.kntc = q.kntc;
+    d.crmax0 = q.crmax0;
+    d.sqrt_tw = q.sqrt_tw;
+    d.inv_dy = q.inv_dy;
+    d.n_transient = p->n_transient;
+    d.key0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
+    d.key1 = (uint32_t)(p->seed >> 32);
+    d.phase_mask = p->debug_phase_mask ? p->debug_phase_mask : (uint32_t)DSMC_PHASE_ALL;
+    for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 4; ++a) d.buf[b][a] = base + q.off_buf[b][a];
+    d.cell = (int32_t*)(base + q.off_cell);
+    d.counts = (int32_t*)(base + q.off_counts);
+    d.segsum = (int32_t*)(base + q.off_segsum);
+    d.count = (int32_t*)(base + q.off_count);
+    d.offset = (int32_t*)(base + q.off_offset);
+    d.crmax = (double*)(base + q.off_crmax);
+    d.rem = (double*)(base + q.off_rem);
+    d.acc = (double*)(base + q.off_acc);
+    d.est = (double*)(base + q.off_est);
+    d.sc = (DevScalars*)(base + q.off_sc);
+    h->d_desc = (InstDesc*)(base + q.off_desc);
+    device_max_lds();
+    const char* where = "copy of the instance descriptor";
+    hipError_t e = hipMemcpyAsync(h->d_desc, &h->desc, sizeof(InstDesc), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+        where = "init kernel launch";
+        launch_init(h->desc, h->d_desc, (Mode)q.mode, h->stream);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        where = "init synchronise";
+        e = hipStreamSynchronize(h->stream);
+    }
+    if (e != hipSuccess) {
+        if (h->owns_mem) (void)hipFree(h->mem);
+        delete h;
+        return fail(nullptr, DSMC_ERR_DEVICE, std::string("create: ") + where + ": " + hipGetErrorString(e));
+    }
+    *out = h;
+    return DSMC_OK;
+}
+
+int dsmc_step(dsmc_handle* h, int64_t n_steps) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    if (h->group) return fail(&h->err, DSMC_ERR_STATE, "handle belongs to a group; use dsmc_group_step");
+    if (n_steps < 0) return fail(&h->err, DSMC_ERR_INVALID_ARG, "n_steps < 0");
+    if (!h->solo) {
+        h->solo = new (std::nothrow) dsmc_group();
+        if (!h->solo) return fail(&h->err, DSMC_ERR_OUT_OF_MEMORY, "host allocation failed");
+        group_init(h->solo, h->stream, true);
+        h->solo->mode = h->plan.mode;
+        h->solo->members.push_back(h);
+    }
+    const int r = enqueue_steps(h->solo, n_steps);
+    if (r) h->err = h->solo->err;
+    else if (n_steps > 0 && (h->solo->phase & DSMC_PHASE_SORT)) h->sorted = true;
+    return r;
+}
+
+int dsmc_sync(dsmc_handle* h) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    return sync_check(h);
+}
+
+int dsmc_sample(dsmc_handle* h, dsmc_moments* out, int reset_window) {
+    if (!h || !out) return fail(h ? &h->err : nullptr, DSMC_ERR_INVALID_ARG, "NULL argument");
+    if (out->n_cells < h->plan.C) return fail(&h->err, DSMC_ERR_INVALID_ARG, "moments.n_cells smaller than the handle's cells");
+    hipStream_t s = stream_of(h);
+    launch_finalize(h->d_desc, 1, s);
+    HIP_TRY(&h->err, hipGetLastError());
+    const int C = h->plan.C;
+    std::vector<double> est((size_t)kEstPerCell * C + 2);
+    HIP_TRY(&h->err, hipMemcpyAsync(est.data(), h->desc.est, est.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> raw;
+    if (out->raw_sums) {
+        raw.resize((size_t)h->plan.Cc * kMoments);
+        HIP_TRY(&h->err, hipMemcpyAsync(raw.data(), h->desc.acc, raw.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    DevScalars sc;
+    HIP_TRY(&h->err, hipMemcpyAsync(&sc, h->desc.sc, sizeof sc, hipMemcpyDeviceToHost, s));
+    int r = sync_check(h);
+    if (r) return r;
+    double* dst[kEstPerCell] = {out->n, out->ux, out->uy, out->uz, out->T, out->pxy, out->qx, out->qy};
+    for (int m = 0; m < kEstPerCell; ++m)
+        if (dst[m]) std::memcpy(dst[m], est.data() + (size_t)m * C, sizeof(double) * C);
+    if (out->raw_sums) std::memcpy(out->raw_sums, raw.data(), raw.size() * sizeof(double));
+    out->mass_flow = sc.n_sampled ? est[(size_t)kEstPerCell * C] : NAN;
+    out->n_sampled_steps = sc.n_sampled;
+    out->n_collisions = (int64_t)sc.n_coll;
+    if (reset_window) {
+        launch_reset_window(h->d_desc, 1, s);
+        HIP_TRY(&h->err, hipGetLastError());
+    }
+    return DSMC_OK;
+}
+
+int dsmc_get_state(dsmc_handle* h, void* y, void* vx, void* vy, void* vz, int32_t* cell,
+                   uint64_t* step) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    int r = sync_check(h);
+    if (r) return r;
+    DevScalars sc;
+    HIP_TRY(&h->err, hipMemcpy(&sc, h->desc.sc, sizeof sc, hipMemcpyDeviceToHost));
+    const int b = (int)(sc.step_done & 1);
+    const size_t bytes = (size_t)h->plan.N * h->plan.rb;
+    void* outs[4] = {y, vx, vy, vz};
+    for (int a = 0; a < 4; ++a)
+        if (outs[a]) HIP_TRY(&h->err, hipMemcpy(outs[a], h->desc.buf[b][a], bytes, hipMemcpyDeviceToHost));
+    if (cell) {
+        if (h->sorted) {
+            const size_t c = (size_t)h->plan.Cc;
+            std::vector<int32_t> count(c), offset(c);
+            HIP_TRY(&h->err, hipMemcpy(count.data(), h->desc.count, c * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(&h->err, hipMemcpy(offset.data(), h->desc.offset, c * 4, hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < c; ++k)
+                for (int32_t i = 0; i < count[k]; ++i) cell[offset[k] + i] = (int32_t)k;
+        } else {
+            HIP_TRY(&h->err, hipMemcpy(cell, h->desc.cell, (size_t)h->plan.N * 4, hipMemcpyDeviceToHost));
+        }
+    }
+    if (step) *step = (uint64_t)sc.step_done;
+    return DSMC_OK;
+}
+
+int dsmc_set_state(dsmc_handle* h, const void* y, const void* vx, const void* vy, const void* vz,
+                   const int32_t* cell, uint64_t step) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    int r = sync_check(h);
+    if (r) return r;
+    DevScalars sc;
+    HIP_TRY(&h->err, hipMemcpy(&sc, h->desc.sc, sizeof sc, hipMemcpyDeviceToHost));
+    const int b_old = (int)(sc.step_done & 1);
+    sc.step_done = (int64_t)step;
+    const int b = (int)(step & 1);
+    const size_t bytes = (size_t)h->plan.N * h->plan.rb;
+    const void* ins[4] = {y, vx, vy, vz};
+    for (int a = 0; a < 4; ++a) {
+        if (ins[a]) {
+            HIP_TRY(&h->err, hipMemcpy(h->desc.buf[b][a], ins[a], bytes, hipMemcpyHostToDevice));
+        } else if (b != b_old) {
+            // arrays not given keep their current values, in the new buffer
+            HIP_TRY(&h->err, hipMemcpy(h->desc.buf[b][a], h->desc.buf[b_old][a], bytes, hipMemcpyDeviceToDevice));
+        }
+    }
+    if (cell) HIP_TRY(&h->err, hipMemcpy(h->desc.cell, cell, (size_t)h->plan.N * 4, hipMemcpyHostToDevice));
+    HIP_TRY(&h->err, hipMemcpy(h->desc.sc, &sc, sizeof sc, hipMemcpyHostToDevice));
+    h->sorted = false;
+    return DSMC_OK;
+}
+
+int dsmc_get_cells(dsmc_handle* h, double* crmax, double* rem, int32_t* count, int32_t* offset) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    int r = sync_check(h);
+    if (r) return r;
+    const size_t c = (size_t)h->plan.Cc;
+    if (crmax) HIP_TRY(&h->err, hipMemcpy(crmax, h->desc.crmax, c * 8, hipMemcpyDeviceToHost));
+    if (rem) HIP_TRY(&h->err, hipMemcpy(rem, h->desc.rem, c * 8, hipMemcpyDeviceToHost));
+    if (count) HIP_TRY(&h->err, hipMemcpy(count, h->desc.count, c * 4, hipMemcpyDeviceToHost));
+    if (offset) HIP_TRY(&h->err, hipMemcpy(offset, h->desc.offset, c * 4, hipMemcpyDeviceToHost));
+    return DSMC_OK;
+}
+
+int dsmc_set_cells(dsmc_handle* h, const double* crmax, const double* rem, const int32_t* count,
+                   const int32_t* offset) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    int r = sync_check(h);
+    if (r) return r;
+    const size_t c = (size_t)h->plan.Cc;
+    if (count && offset) {
+        int64_t tot = 0;
+        for (size_t i = 0; i < c; ++i) {
+            if (count[i] < 0 || offset[i] != tot) return fail(&h->err, DSMC_ERR_INVALID_ARG, "offsets must be the exclusive scan of counts");
+            tot += count[i];
+        }
+        if (tot != h->plan.N) return fail(&h->err, DSMC_ERR_INVALID_ARG, "counts must add up to N");
+    } else if (count || offset) {
+        return fail(&h->err, DSMC_ERR_INVALID_ARG, "count and offset must be given together");
+    }
+    if (crmax) HIP_TRY(&h->err, hipMemcpy(h->desc.crmax, crmax, c * 8, hipMemcpyHostToDevice));
+    if (rem) HIP_TRY(&h->err, hipMemcpy(h->desc.rem, rem, c * 8, hipMemcpyHostToDevice));
+    if (count) HIP_TRY(&h->err, hipMemcpy(h->desc.count, count, c * 4, hipMemcpyHostToDevice));
+    if (offset) HIP_TRY(&h->err, hipMemcpy(h->desc.offset, offset, c * 4, hipMemcpyHostToDevice));
+    return DSMC_OK;
+}
+
+int dsmc_info(const dsmc_handle* h, int32_t* n_particles, int32_t* n_coll_cells, double* c6) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    if (n_particles) *n_particles = h->plan.N;
+    if (n_coll_cells) *n_coll_cells = h->plan.Cc;
+    if (c6) {
+        c6[0] = h->plan.dt;
+        c6[1] = h->plan.g;
+        c6[2] = h->plan.kntc;
+        c6[3] = h->plan.crmax0;
+        c6[4] = h->plan.inv_dy;
+        c6[5] = h->plan.lam;
+    }
+    return DSMC_OK;
+}
+
+int dsmc_destroy(dsmc_handle* h) {
+    if (!h) return DSMC_OK;
+    if (h->group) dsmc_group_remove(h->group, h);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->solo) group_free(h->solo);
+    if (h->owns_mem && h->mem) (void)hipFree(h->mem);
+    delete h;
+    return DSMC_OK;
+}
+
+int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
+    if (!h || !phase_ms || n_steps < 1) return fail(h ? &h->err : nullptr, DSMC_ERR_INVALID_ARG, "bad argument");
+    dsmc_group* g = h->group;
+    if (!g) {
+        // make sure the private group exists and is current
+        int r = dsmc_step(h, 0);
+        if (r) return r;
+        if (!h->solo) {
+            h->solo = new (std::nothrow) dsmc_group();
+            if (!h->solo) return fail(&h->err, DSMC_ERR_OUT_OF_MEMORY, "host allocation failed");
+            group_init(h->solo, h->stream, true);
+            h->solo->mode = h->plan.mode;
+            h->solo->members.push_back(h);
+        }
+        g = h->solo;
+    }
+    if (g->dirty) {
+        const int r = rebuild(g);
+        if (r) return r;
+    }
+    hipEvent_t ev[7];
+    for (int i = 0; i < 7; ++i) HIP_TRY(&h->err, hipEventCreate(&ev[i]));
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = DSMC_OK;
+    for (int64_t k = 0; k < n_steps && rc == DSMC_OK; ++k) {
+        launch_step_timed(g->work, (Mode)g->mode, g->phase, g->stream, ev);
+        if (hipEventSynchronize(ev[6]) != hipSuccess) {
+            rc = fail(&h->err, DSMC_ERR_DEVICE, "event synchronise failed");
+            break;
+        }
+        for (int i = 0; i < 6; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) acc[i] += ms;
+        }
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+    for (int i = 0; i < 7; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc) return rc;
+    if (g->phase & DSMC_PHASE_SORT) {
+        if (g->solo) h->sorted = true;
+        else for (dsmc_handle* m : g->members) m->sorted = true;
+    }
+    for (int i = 0; i < 6; ++i) phase_ms[i] = acc[i];
+    phase_ms[6] = acc[0] + acc[1] + acc[2] + acc[3] + acc[4] + acc[5];
+    phase_ms[7] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return sync_check(h);
+}
+
+// ---------------------------------------------------------------- groups
+int dsmc_group_create(void* stream, dsmc_group** out) {
+    if (out) *out = nullptr;
+    if (!out) return fail(nullptr, DSMC_ERR_INVALID_ARG, "out is NULL");
+    dsmc_group* g = new (std::nothrow) dsmc_group();
+    if (!g) return fail(nullptr, DSMC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    group_init(g, (hipStream_t)stream, false);
+    *out = g;
+    return DSMC_OK;
+}
+
+int dsmc_group_add(dsmc_group* g, dsmc_handle* h) {
+    if (!g || !h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "NULL argument");
+    if (h->group) return fail(&g->err, DSMC_ERR_INVALID_ARG, "handle already belongs to a group");
+    if (g->mode >= 0 && !g->members.empty() && g->mode != h->plan.mode)
+        return fail(&g->err, DSMC_ERR_INVALID_ARG, "precision differs from the group's");
+    HIP_TRY(&g->err, hipStreamSynchronize(h->stream));
+    g->mode = h->plan.mode;
+    g->members.push_back(h);
+    h->group = g;
+    g->dirty = true;
+    return DSMC_OK;
+}
+
+int dsmc_group_remove(dsmc_group* g, dsmc_handle* h) {
+    if (!g || !h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "NULL argument");
+    auto it = std::find(g->members.begin(), g->members.end(), h);
+    if (it == g->members.end()) return fail(&g->err, DSMC_ERR_INVALID_ARG, "handle is not in this group");
+    HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
+    g->members.erase(it);
+    h->group = nullptr;
+    g->dirty = true;
+    return DSMC_OK;
+}
+
+int dsmc_group_step(dsmc_group* g, int64_t n_steps) {
+    if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
+    const int r = enqueue_steps(g, n_steps);
+    if (r == DSMC_OK && n_steps > 0)
+        for (dsmc_handle* h : g->members) h->sorted = true;
+    return r;
+}
+
+int dsmc_group_sync(dsmc_group* g) {
+    if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
+    HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
+    for (dsmc_handle* h : g->members) {
+        const int r = sync_check(h);
+        if (r) return r;
+    }
+    return DSMC_OK;
+}
+
+int dsmc_group_size(const dsmc_group* g, int32_t* n) {
+    if (!g || !n) return fail(nullptr, DSMC_ERR_INVALID_ARG, "NULL argument");
+    *n = (int32_t)g->members.size();
+    return DSMC_OK;
+}
+
+int dsmc_group_destroy(dsmc_group* g) {
+    if (!g) return DSMC_OK;
+    if (g->stream || !g->members.empty()) (void)hipStreamSynchronize(g->stream);
+    for (dsmc_handle* h : g->members) h->group = nullptr;
+    g->members.clear();
+    group_free(g);
+    return DSMC_OK;
+}
+
+int dsmc_group_set_tuning(dsmc_group* g, int32_t tile_mult, int32_t cells_per_block) {
+    if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
+    if (tile_mult < 0 || tile_mult > 64 || cells_per_block < 0 || cells_per_block > 1024)
+        return fail(&g->err, DSMC_ERR_INVALID_ARG, "tuning out of range");
+    g->tile_mult = tile_mult;
+    g->cpb = cells_per_block;
+    g->dirty = true;
+    return DSMC_OK;
+}
+
+int dsmc_group_autotune(dsmc_group* g, int32_t* tile_mult_out, int32_t* cpb_out) {
+    if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
+    (void)tile_mult_out;
+    (void)cpb_out;
+    return fail(&g->err, DSMC_ERR_STATE, "autotuning not available yet");
+}
+
+}  // extern "C"

@@ -18,3 +18,19 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+def _gpu_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def pytest_collection_modifyitems(config, items):
+    if any(item.get_closest_marker("gpu") for item in items) and not _gpu_available():
+        skip = pytest.mark.skip(reason="no GPU visible")
+        for item in items:
+            if item.get_closest_marker("gpu"):
+                item.add_marker(skip)

@@ -1,0 +1,102 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/dsmc.h declares, and rejects bad arguments on the host before any
+device call."""
+import ctypes as ct
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dsmc.h")
+
+
+@pytest.fixture(scope="module")
+def D():
+    from paper_2311_14140_amd import dsmc
+    return dsmc
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dsmc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("dsmc_create", "dsmc_step", "dsmc_sample", "dsmc_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(D):
+    lib = ct.CDLL(D.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(D.EXPORTS)
+
+
+def _params(D, **kw):
+    p = D.dsmc_params()
+    assert D.lib.dsmc_params_init(ct.byref(p)) == 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _fp(D, p):
+    out = ct.c_uint64(12345)
+    r = D.lib.dsmc_footprint_bytes(ct.byref(p), ct.byref(out))
+    return r, out.value
+
+
+@pytest.mark.parametrize("field,value", [
+    ("kn", 0.0), ("kn", -1.0), ("kn", math.nan), ("kn", math.inf),
+    ("body_force", math.nan), ("wall_temperature", 0.0), ("wall_temperature", math.inf),
+    ("dt", math.nan), ("n_cells", 0), ("particles_per_cell", 0), ("n_sub", 0),
+    ("n_transient", -1), ("precision", 7), ("struct_size", 8), ("debug_phase_mask", 99),
+    ("n_cells", 70000), ("particles_per_cell", 2**30),
+])
+def test_invalid_params_rejected_and_out_untouched(D, field, value):
+    p = _params(D, **{field: value})
+    r, out = _fp(D, p)
+    assert r == D.DSMC_ERR_INVALID_ARG
+    assert out == 12345
+    h = ct.c_void_p(0xDEAD)
+    assert D.lib.dsmc_create(ct.byref(p), None, None, 0, ct.byref(h)) == D.DSMC_ERR_INVALID_ARG
+    assert h.value is None
+    assert D.lib.dsmc_last_error(None)
+
+
+def test_footprint_monotone(D):
+    base = _fp(D, _params(D, n_cells=100, particles_per_cell=50))
+    assert base[0] == 0 and base[1] > 0
+    more_p = _fp(D, _params(D, n_cells=100, particles_per_cell=500))[1]
+    more_c = _fp(D, _params(D, n_cells=400, particles_per_cell=50))[1]
+    fp32 = _fp(D, _params(D, n_cells=100, particles_per_cell=500, precision=D.DSMC_FP32_FAST))[1]
+    assert more_p > base[1] and more_c > base[1]
+    assert fp32 < more_p
+    # at least the particle records: two buffers of 4 reals plus a cell id
+    assert more_p >= 100 * 500 * (2 * 4 * 8 + 4)
+
+
+def test_arena_too_small_is_out_of_memory(D):
+    p = _params(D)
+    r, need = _fp(D, p)
+    h = ct.c_void_p()
+    assert D.lib.dsmc_create(ct.byref(p), None, ct.c_void_p(4096), need - 1, ct.byref(h)) == \
+        D.DSMC_ERR_OUT_OF_MEMORY
+    assert h.value is None
+
+
+def test_null_safety(D):
+    assert D.lib.dsmc_destroy(None) == 0
+    assert D.lib.dsmc_group_destroy(None) == 0
+    assert D.lib.dsmc_step(None, 1) == D.DSMC_ERR_INVALID_ARG
+    assert D.lib.dsmc_sample(None, None, 0) == D.DSMC_ERR_INVALID_ARG
+    assert D.lib.dsmc_params_init(None) == D.DSMC_ERR_INVALID_ARG
+    assert D.lib.dsmc_group_create(None, None) == D.DSMC_ERR_INVALID_ARG
+    for code in (0, -1, -2, -3, -4, -5):
+        assert D.lib.dsmc_status_string(code)
+    assert D.lib.dsmc_status_string(-99) == b"unknown status"
