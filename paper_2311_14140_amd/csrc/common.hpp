@@ -19,12 +19,15 @@ constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
 struct DevScalars {
     int64_t step_done;            // steps completed
     int64_t n_sampled;            // sampled steps in the window
-    unsigned long long n_coll;    // accepted collisions in the window
-    unsigned long long n_hits;    // wall hits since creation
     int32_t status;               // bit 0: non-finite velocity, bit 1: particle count lost
-    int32_t pad_;
+    int32_t pad_[3];
 };
 
+// Counters are kept per collision cell and written only by the wavefront
+// that owns the cell: a single device-wide counter updated by every
+// workgroup at the end of a kernel serialises hundreds of same-address
+// atomics and costs far more than the kernel's own work.
+//
 // Everything a kernel needs to know about one instance.  Particle arrays are
 // structure-of-arrays: buf[b][0..3] = y, vx, vy, vz of buffer b.  After step
 // s the state lives in buffer (s & 1): the move of step s works in place on
@@ -46,7 +49,8 @@ struct InstDesc {
     double* crmax;     // Cc
     double* rem;       // Cc
     double* acc;       // Cc * kMoments
-    double* est;       // kEstPerCell * C + 2 (mass flow, sampled steps)
+    uint32_t* ncoll;   // Cc: accepted collisions in the window, per collision cell
+    double* est;       // kEstPerCell * C + 3 (mass flow, sampled steps, collisions)
     DevScalars* sc;
 };
 

@@ -76,13 +76,12 @@ __global__ void k_init(const InstDesc* __restrict__ descs) {
         d.rem[p] = 0.0;
         d.count[p] = 0;
         d.offset[p] = 0;
+        d.ncoll[p] = 0u;
         for (int m = 0; m < kMoments; ++m) d.acc[(size_t)p * kMoments + m] = 0.0;
     }
     if (p == 0) {
         d.sc->step_done = 0;
         d.sc->n_sampled = 0;
-        d.sc->n_coll = 0;
-        d.sc->n_hits = 0;
         d.sc->status = 0;
     }
 }
@@ -139,21 +138,18 @@ template <class R, bool kMove>
 __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* __restrict__ descs,
                                                                const int2* __restrict__ work) {
     extern __shared__ int hist[];
-    __shared__ int blk_hits, blk_bad;
+    __shared__ int blk_bad;
     const int2 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
     const int Cc = d.Cc;
     for (int c = threadIdx.x; c < Cc; c += blockDim.x) hist[c] = 0;
-    if (threadIdx.x == 0) {
-        blk_hits = 0;
-        blk_bad = 0;
-    }
+    if (threadIdx.x == 0) blk_bad = 0;
     __syncthreads();
     const int64_t s = d.sc->step_done + 1;
     const P4<R> b = particles<R>(d, (int)((s - 1) & 1));
     const int start = w.y * d.tile_items;
     const int end = min(start + d.tile_items, d.N);
-    int hits = 0, bad = 0;
+    int bad = 0;
     for (int p = start + (int)threadIdx.x; p < end; p += blockDim.x) {
         int c;
         if (kMove) {
@@ -165,7 +161,6 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* 
                 b.vy[p] = vy;
                 b.vz[p] = vz;
             }
-            hits += h;
             bad |= !(isfinite(vx) && isfinite(vy) && isfinite(vz));
             c = cell_of<R>(d, y);
             d.cell[p] = c;
@@ -174,17 +169,12 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* 
         }
         atomicAdd(&hist[c], 1);
     }
-    if (kMove) {
-        if (hits) atomicAdd(&blk_hits, hits);
-        if (bad) atomicOr(&blk_bad, 1);
-    }
+    if (kMove && bad) atomicOr(&blk_bad, 1);
     __syncthreads();
     int* row = d.counts + (size_t)w.y * Cc;
     for (int c = threadIdx.x; c < Cc; c += blockDim.x) row[c] = hist[c];
-    if (kMove && threadIdx.x == 0) {
-        if (blk_hits) atomicAdd(&d.sc->n_hits, (unsigned long long)blk_hits);
-        if (blk_bad) atomicOr(&d.sc->status, 1);
-    }
+    // error path only: a non-finite velocity was seen in this tile
+    if (kMove && threadIdx.x == 0 && blk_bad) atomicOr(&d.sc->status, 1);
 }
 
 // ------------------------------------------------------- column scans
@@ -420,7 +410,7 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
     const int c = w.y + (int)threadIdx.x;
     const int64_t s = d.sc->step_done;
     const bool sample = (d.phase_mask & kPhaseSample) && s > d.n_transient;
-    unsigned long long ncoll = 0;
+    uint32_t ncoll = 0;
     if (c < w.z) {
         const P4<double> b = particles<double>(d, (int)(s & 1));
         const int n = d.count[c], o = d.offset[c];
@@ -466,6 +456,7 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
                 }
             }
             d.crmax[c] = crm;
+            if (ncoll) d.ncoll[c] += ncoll;
         }
         if (sample) {
             Mom m;
@@ -476,7 +467,6 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
             for (int k = 0; k < kMoments; ++k) a[k] += m.s[k];
         }
     }
-    if (ncoll) atomicAdd(&d.sc->n_coll, ncoll);
 }
 
 // ------------------------------------------------------- collide (fast)
@@ -552,7 +542,6 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long lt = lanes_below(lane);
     uint32_t* tab = claims + wv * kClaimTable;
-    unsigned long long ncoll = 0;
     for (int c = c0 + wv; c < c1; c += nw) {
         const int nc = d.count[c];
         const int o = d.offset[c] - s0;
@@ -564,6 +553,7 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
             const int64_t M = (int64_t)mf;
             const R crmr = (R)crm0;
             R lane_max = R(0);
+            uint32_t lane_coll = 0;
             int64_t next = 0;
             int64_t myk = -1;
             int mi = 0, mj = 0;
@@ -621,7 +611,7 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
                         vx[j] = cmx - hh * dx;
                         vy[j] = cmy - hh * dy;
                         vz[j] = cmz - hh * dz;
-                        ++ncoll;
+                        ++lane_coll;
                     }
                     myk = -1;
                 }
@@ -634,7 +624,13 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
                 const double other = __shfl_xor(mx, off, 64);
                 mx = other > mx ? other : mx;
             }
-            if (lane == 0 && mx > crm0) d.crmax[c] = mx;
+            uint32_t cc = lane_coll;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) cc += __shfl_xor(cc, off, 64);
+            if (lane == 0) {
+                if (mx > crm0) d.crmax[c] = mx;
+                d.ncoll[c] += cc;
+            }
         }
         if (sample) {
             Mom m;
@@ -659,7 +655,6 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
             g.vz[s0 + i] = vz[i];
         }
     }
-    if (ncoll) atomicAdd(&d.sc->n_coll, ncoll);
 }
 
 // ----------------------------------------------------------- estimators
@@ -704,6 +699,11 @@ __global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ d
         e[6 * C + c] = (0.5 * n_c * cx) / v0;
         e[7 * C + c] = (0.5 * n_c * cy) / v0;
     }
+    __shared__ unsigned long long coll_part[256];
+    unsigned long long cs = 0;
+    for (int c = threadIdx.x; c < d.Cc; c += blockDim.x) cs += d.ncoll[c];
+    coll_part[threadIdx.x] = cs;
+    __syncthreads();
     if (threadIdx.x == 0) {
         double q = 0.0;
         for (int c = 0; c < C; ++c) {
@@ -711,8 +711,11 @@ __global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ d
             for (int k = 0; k < ns; ++k) sx += d.acc[((size_t)c * ns + k) * kMoments + 1];
             q += sx;
         }
+        unsigned long long tot = 0;
+        for (int t = 0; t < (int)blockDim.x; ++t) tot += coll_part[t];
         d.est[kEstPerCell * C] = (q / (K * N)) / v0;
         d.est[kEstPerCell * C + 1] = K;
+        d.est[kEstPerCell * C + 2] = (double)tot;
     }
 }
 
@@ -720,10 +723,8 @@ __global__ __launch_bounds__(256) void k_reset_window(const InstDesc* __restrict
     const InstDesc& d = descs[blockIdx.x];
     const size_t n = (size_t)d.Cc * kMoments;
     for (size_t i = threadIdx.x; i < n; i += blockDim.x) d.acc[i] = 0.0;
-    if (threadIdx.x == 0) {
-        d.sc->n_sampled = 0;
-        d.sc->n_coll = 0;
-    }
+    for (int c = threadIdx.x; c < d.Cc; c += blockDim.x) d.ncoll[c] = 0u;
+    if (threadIdx.x == 0) d.sc->n_sampled = 0;
 }
 
 template <class R>

@@ -52,7 +52,7 @@ struct Plan {
     double H = 1.0, lam = 0, dt = 0, g = 0, kntc = 0, crmax0 = 0, sqrt_tw = 1, inv_dy = 0;
     // arena offsets
     uint64_t off_buf[2][4], off_cell, off_counts, off_segsum, off_count, off_offset, off_crmax,
-        off_rem, off_acc, off_est, off_sc, off_desc, total;
+        off_rem, off_acc, off_ncoll, off_est, off_sc, off_desc, total;
 };
 
 int base_items_per_thread(int32_t N, int32_t Cc) {
@@ -131,7 +131,8 @@ Plan make_plan(const dsmc_params* p) {
     q.off_crmax = take((uint64_t)q.Cc * 8);
     q.off_rem = take((uint64_t)q.Cc * 8);
     q.off_acc = take((uint64_t)q.Cc * kMoments * 8);
-    q.off_est = take(((uint64_t)kEstPerCell * q.C + 2) * 8);
+    q.off_ncoll = take((uint64_t)q.Cc * 4);
+    q.off_est = take(((uint64_t)kEstPerCell * q.C + 3) * 8);
     q.off_sc = take(sizeof(DevScalars));
     q.off_desc = take(sizeof(InstDesc));
     q.total = o + kAlign;  // slack to align an unaligned arena
@@ -476,6 +477,7 @@ int dsmc_create(const dsmc_params* p, void* stream, void* arena, uint64_t arena_
     d.crmax = (double*)(base + q.off_crmax);
     d.rem = (double*)(base + q.off_rem);
     d.acc = (double*)(base + q.off_acc);
+    d.ncoll = (uint32_t*)(base + q.off_ncoll);
     d.est = (double*)(base + q.off_est);
     d.sc = (DevScalars*)(base + q.off_sc);
     h->d_desc = (InstDesc*)(base + q.off_desc);
@@ -529,7 +531,7 @@ int dsmc_sample(dsmc_handle* h, dsmc_moments* out, int reset_window) {
     launch_finalize(h->d_desc, 1, s);
     HIP_TRY(&h->err, hipGetLastError());
     const int C = h->plan.C;
-    std::vector<double> est((size_t)kEstPerCell * C + 2);
+    std::vector<double> est((size_t)kEstPerCell * C + 3);
     HIP_TRY(&h->err, hipMemcpyAsync(est.data(), h->desc.est, est.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     std::vector<double> raw;
     if (out->raw_sums) {
@@ -546,7 +548,7 @@ int dsmc_sample(dsmc_handle* h, dsmc_moments* out, int reset_window) {
     if (out->raw_sums) std::memcpy(out->raw_sums, raw.data(), raw.size() * sizeof(double));
     out->mass_flow = sc.n_sampled ? est[(size_t)kEstPerCell * C] : NAN;
     out->n_sampled_steps = sc.n_sampled;
-    out->n_collisions = (int64_t)sc.n_coll;
+    out->n_collisions = (int64_t)est[(size_t)kEstPerCell * C + 2];
     if (reset_window) {
         launch_reset_window(h->d_desc, 1, s);
         HIP_TRY(&h->err, hipGetLastError());
