@@ -30,24 +30,21 @@ METRIC = ("particle-steps/s at fixed moment accuracy (FP32 batched vs FP64 plain
           "p50/p99 solve latency")
 
 
-def kernel_bytes(phase: str, N: int, Cc: int, tiles: int, rb: int, coll_frac: float,
-                 sampling: bool) -> float:
-    """Algorithmic HBM bytes of one launch of a phase kernel (per-particle
-    record traffic the method must move, plus its per-cell and per-tile
-    tables)."""
-    if phase == "move_hist":   # read y, v; write y, vx, cell; histogram rows
-        return N * (4 * rb + 2 * rb + 4) + tiles * Cc * 4
-    if phase == "scatter":     # read cell + record, write record; base rows
-        return N * (4 + 4 * rb + 4 * rb) + tiles * Cc * 4
+def kernel_bytes(phase: str, N: int, Cc: int, rb: int, coll_frac: float, sampling: bool) -> float:
+    """Algorithmic HBM bytes of one launch of a phase kernel: the particle
+    record and per-cell traffic the method itself must move (library tables
+    such as per-tile histograms are not counted)."""
+    if phase == "move_hist":   # read y, v; write y, vx and the cell index
+        return N * (4 * rb + 2 * rb + 4)
+    if phase == "scatter":     # read cell + record, write the record
+        return N * (4 + 4 * rb + 4 * rb)
     if phase == "collide":     # read v, write the collided particles' v; cell tables
-        b = N * 3 * rb + coll_frac * N * 3 * rb + Cc * (8 + 8 + 4 + 4)
+        b = N * 3 * rb + coll_frac * N * 3 * rb + Cc * (8 + 8 + 4 + 4 + 4)
         if sampling:
             b += Cc * 12 * 8 * 2
         return b
-    if phase in ("colsum", "colprefix"):
-        return tiles * Cc * 4 * (1 if phase == "colsum" else 2)
     if phase == "scan":
-        return Cc * 4 * 4
+        return Cc * 4 * 2
     return 0.0
 
 
@@ -117,16 +114,11 @@ def main():
     # ---- per-kernel durations: HIP events around every kernel on the
     # library's stream, over separately launched steps of the same run
     prof = s.profile(args.profile_steps)
-    tile_items = None
-    import numpy as np  # noqa: F401
-    # tiles of the instance as the library planned them
-    from paper_2311_14140_amd.dsmc import lib  # noqa: F401
-    tiles = max(1, math.ceil(N / max(256, 256 * max(1, min(64, math.ceil(4 * Cc / 256))))))
     kern = {k: prof[k] / args.profile_steps for k in dsmc.Solver.PHASES}
     dom = max(kern, key=kern.get)
-    dom_bytes = kernel_bytes(dom, N, Cc, tiles, rb, coll_frac, True)
+    dom_bytes = kernel_bytes(dom, N, Cc, rb, coll_frac, True)
     achieved = dom_bytes / (kern[dom] * 1e-3) / 1e9
-    step_bytes = sum(kernel_bytes(k, N, Cc, tiles, rb, coll_frac, True) for k in kern)
+    step_bytes = sum(kernel_bytes(k, N, Cc, rb, coll_frac, True) for k in kern)
     print("# per-kernel ms/step: " + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()),
           file=sys.stderr, flush=True)
     s.close()

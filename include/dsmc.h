@@ -83,7 +83,8 @@ typedef struct dsmc_params {
     double dt;                  /* time step; <= 0 selects 0.2 min(lambda, H) / sqrt(2) */
     int32_t n_cells;            /* sampling cells across the gap, >= 1 */
     int32_t particles_per_cell; /* initial particles per sampling cell, >= 1 */
-    int32_t n_sub;              /* collision cells per sampling cell, >= 1 (1 = plain) */
+    int32_t n_sub;              /* collision cells per sampling cell, >= 1 (1 = plain);
+                                   n_cells * n_sub <= 10240 */
     uint32_t debug_phase_mask;  /* DSMC_PHASE_* subset for tests; 0 = all */
     int64_t n_transient;        /* steps before sampling starts, >= 0 */
     uint64_t seed;              /* key of every random stream */

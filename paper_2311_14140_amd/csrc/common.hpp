@@ -7,12 +7,15 @@ namespace dsmc {
 
 constexpr int kMoments = 12;       // 1, vx, vy, vz, vx2, vy2, vz2, vxvy, vxvz, vyvz, v2vx, v2vy
 constexpr int kEstPerCell = 8;     // n, ux, uy, uz, T, pxy, qx, qy
-constexpr int kParticleThreads = 256;  // threads of the move and scatter kernels
+constexpr int kParticleThreads = 256;  // threads per particle tile (move, scatter)
+constexpr int kScatterWaves = kParticleThreads / 64;  // wavefronts of a scatter tile
 constexpr int kColThreads = 256;       // cells per workgroup of the column-scan kernels
 constexpr int kScanThreads = 1024;     // threads of the per-instance scan kernel
 constexpr int kSegTiles = 32;          // tiles per column-scan segment
 constexpr int kClaimTable = 1024;      // per-wavefront claim table of the fast collide
 constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
+constexpr int kCoopMin = 256;          // cells this full are collided by a whole workgroup
+constexpr int kCoopTable = kFastWaves * kClaimTable;  // its claim table (the wave tables together)
 
 // Scalars an instance keeps on the device so that a step is the same launch
 // sequence every time (and can be replayed from a graph).

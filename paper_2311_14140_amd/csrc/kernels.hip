@@ -270,37 +270,54 @@ __global__ __launch_bounds__(kColThreads) void k_colprefix(const InstDesc* __res
 }
 
 // --------------------------------------------------------------- scatter
-// Stable scatter of one tile.  The tile is walked in rounds of 256 slots in
-// slot order; within a wavefront, equal cells are grouped with ballots (the
-// rank of a slot is the number of lower lanes with the same cell); across the
-// four wavefronts of a round, each wavefront's (cell, count) list is shared in
-// LDS; per-cell running bases live in LDS.  The destination of every slot is
-// therefore base + (number of earlier slots of the tile with the same cell),
-// exactly a stable counting sort.
+// Stable scatter of one tile by a workgroup of four wavefronts, each owning a
+// contiguous quarter of the tile.  A first pass counts each quarter's cells
+// into that wavefront's LDS table; the base of (quarter q, cell c) is then
+// the tile's base for c plus the counts of c in quarters before q.  In the
+// second pass every wavefront walks its quarter in rounds of 64 slots in slot
+// order.  Lanes holding the same cell are found with bit-sliced ballots (one
+// ballot per bit of the cell index, so the cost does not depend on how many
+// distinct cells a round holds); a lane's rank is the number of lower lanes
+// with its cell, and only the owning wavefront advances its table, so a
+// round needs no barrier.  The destination of every slot is base + (number
+// of earlier slots of the tile with the same cell): exactly a stable
+// counting sort.
 template <class R>
 __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __restrict__ descs,
                                                              const int2* __restrict__ work) {
-    extern __shared__ int running[];
-    __shared__ int wl_cell[kParticleThreads / 64][64];
-    __shared__ int wl_cnt[kParticleThreads / 64][64];
-    __shared__ int wl_n[kParticleThreads / 64];
+    extern __shared__ int tables[];  // kScatterWaves x Cc
     const int2 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
     const int Cc = d.Cc;
-    const int* brow = d.counts + (size_t)w.y * Cc;
-    for (int c = threadIdx.x; c < Cc; c += blockDim.x) running[c] = brow[c];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < kScatterWaves * Cc; k += blockDim.x) tables[k] = 0;
     const int64_t s = d.sc->step_done;
     const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
     const P4<R> dst = particles<R>(d, (int)(s & 1));
     const int start = w.y * d.tile_items;
     const int end = min(start + d.tile_items, d.N);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long lt = lanes_below(lane);
+    const int quarter = (((end - start) + kScatterWaves - 1) / kScatterWaves + 63) / 64 * 64;
+    const int q0 = min(start + wv * quarter, end), q1 = min(q0 + quarter, end);
+    int* mine = tables + wv * Cc;
     __syncthreads();
-    for (int base = start; base < end; base += kParticleThreads) {
-        const int i = base + (int)threadIdx.x;
-        const bool valid = i < end;
-        int c = -1;
+    for (int i = q0 + lane; i < q1; i += 64) atomicAdd(&mine[d.cell[i]], 1);
+    __syncthreads();
+    const int* brow = d.counts + (size_t)w.y * Cc;
+    for (int c = threadIdx.x; c < Cc; c += blockDim.x) {
+        int run = brow[c];
+        for (int q = 0; q < kScatterWaves; ++q) {
+            const int v = tables[q * Cc + c];
+            tables[q * Cc + c] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const unsigned long long lt = lanes_below(lane);
+    const int nbits = Cc > 1 ? 32 - __builtin_clz((unsigned)(Cc - 1)) : 0;
+    for (int base = q0; base < q1; base += 64) {
+        const int i = base + lane;
+        const bool valid = i < q1;
+        int c = 0;
         R ry = R(0), rvx = R(0), rvy = R(0), rvz = R(0);
         if (valid) {
             c = d.cell[i];
@@ -309,44 +326,25 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
             rvy = src.vy[i];
             rvz = src.vz[i];
         }
-        unsigned long long remaining = __ballot(valid);
-        unsigned long long mine = 0;
-        int ng = 0;
-        while (remaining) {
-            const int leader = __builtin_ctzll(remaining);
-            const int lc = __shfl(c, leader, 64);
-            const unsigned long long m = __ballot(c == lc);
-            if (c == lc) mine = m;
-            if (lane == leader) {
-                wl_cell[wv][ng] = lc;
-                wl_cnt[wv][ng] = __popcll(m);
-            }
-            ++ng;
-            remaining &= ~m;
+        unsigned long long m = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (c >> b) & 1;
+            const unsigned long long bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
         }
-        if (lane == 0) wl_n[wv] = ng;
-        __syncthreads();
-        int pos = 0;
         if (valid) {
-            pos = running[c] + __popcll(mine & lt);
-            for (int w2 = 0; w2 < wv; ++w2) {
-                const int n2 = wl_n[w2];
-                for (int g2 = 0; g2 < n2; ++g2) {
-                    if (wl_cell[w2][g2] == c) {
-                        pos += wl_cnt[w2][g2];
-                        break;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (valid) {
-            if ((mine & lt) == 0) atomicAdd(&running[c], __popcll(mine));
+            const int pos = mine[c] + __popcll(m & lt);
+            // every lane of the group reads the base before its leader
+            // (lowest lane) advances it: same wavefront, program order
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if ((m & lt) == 0ull) mine[c] = pos + __popcll(m);
             dst.y[pos] = ry;
             dst.vx[pos] = rvx;
             dst.vy[pos] = rvy;
             dst.vz[pos] = rvz;
         }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -471,15 +469,20 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
 
 // ------------------------------------------------------- collide (fast)
 // The same NTC candidates (pair and acceptance drawn per candidate from the
-// cell's counter-based stream) processed 64 at a time by one wavefront per
-// collision cell, on velocities staged in LDS.  Candidates that share a
-// particle with a lower-numbered pending candidate wait for a later round
-// (claims by atomicMin in a per-wavefront LDS table), so every executed
-// candidate sees exactly the velocities of some sequential order: NTC in
-// distribution.  The acceptance test of a candidate uses
-// max(crmax at cell start, its own c_r); crmax is raised at the end of the
-// cell.  Results depend only on the cell's data and stream, not on which
-// workgroup or group the cell runs in.
+// cell's counter-based stream) processed in parallel rounds on velocities
+// staged in LDS.  A candidate that shares a particle with a lower-numbered
+// pending candidate waits for a later round (claims by atomicMin in an LDS
+// table), so every executed candidate sees exactly the velocities of some
+// sequential order: NTC in distribution.  The acceptance test of a candidate
+// uses max(crmax at cell start, its own c_r); crmax is raised at the end of
+// the cell.
+//
+// Cells with at least kCoopMin particles are processed by the whole
+// workgroup in rounds of blockDim candidates; smaller cells by one wavefront
+// each in rounds of 64.  The mode depends only on the cell's particle count,
+// so results depend only on the cell's data and stream, not on which
+// workgroup, launch shape or group the cell runs in.
+
 template <class R> struct Cand;
 template <> struct Cand<float> {
     __device__ __forceinline__ static void draw(Stream& st, float& a, float& b, float& c) {
@@ -505,14 +508,223 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
     return v;
 }
 
+// One pending candidate of a lane.
+template <class R> struct Pend {
+    int64_t k;
+    int i, j;
+    R acc;
+};
+
+template <class R>
+__device__ __forceinline__ void draw_candidate(const InstDesc& d, uint32_t s, int c, int nc,
+                                               int64_t k, Pend<R>& p, Stream& st) {
+    st = Stream(d.key0, d.key1, s, (uint32_t)c, (uint32_t)k, kTagColl);
+    R ua, ub;
+    Cand<R>::draw(st, ua, ub, p.acc);
+    p.k = k;
+    p.i = min((int)(ua * (R)nc), nc - 1);
+    p.j = min((int)(ub * (R)(nc - 1)), nc - 2);
+    if (p.j >= p.i) ++p.j;
+}
+
+// Execute a candidate that owns both of its particles.
+template <class R>
+__device__ __forceinline__ void run_candidate(Pend<R>& p, Stream& st, R crmr, R* vx, R* vy,
+                                              R* vz, int o, R& lane_max, uint32_t& lane_coll) {
+    const int i = o + p.i, j = o + p.j;
+    const R xi = vx[i], yi = vy[i], zi = vz[i];
+    const R xj = vx[j], yj = vy[j], zj = vz[j];
+    const R crx = xi - xj, cry = yi - yj, crz = zi - zj;
+    const R cr = Num<R>::sqrt((crx * crx + cry * cry) + crz * crz);
+    lane_max = cr > lane_max ? cr : lane_max;
+    const R cm = cr > crmr ? cr : crmr;
+    if (p.acc * cm < cr) {
+        R dx, dy, dz;
+        sphere_point<R>(st, dx, dy, dz);
+        const R cmx = R(0.5) * (xi + xj), cmy = R(0.5) * (yi + yj), cmz = R(0.5) * (zi + zj);
+        const R hh = R(0.5) * cr;
+        vx[i] = cmx + hh * dx;
+        vy[i] = cmy + hh * dy;
+        vz[i] = cmz + hh * dz;
+        vx[j] = cmx - hh * dx;
+        vy[j] = cmy - hh * dy;
+        vz[j] = cmz - hh * dz;
+        ++lane_coll;
+    }
+    p.k = -1;
+}
+
+// NTC of one cell by one wavefront (rounds of 64 candidates).
+template <class R>
+__device__ void wave_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, R* vx, R* vy,
+                         R* vz, uint32_t* tab) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = lanes_below(lane);
+    const double crm0 = d.crmax[c];
+    const double mreal = (((0.5 * (double)nc) * (double)(nc - 1)) * crm0) * d.kntc + d.rem[c];
+    const double mf = floor(mreal);
+    const int64_t M = (int64_t)mf;
+    const R crmr = (R)crm0;
+    R lane_max = R(0);
+    uint32_t lane_coll = 0;
+    int64_t next = 0;
+    Pend<R> p;
+    p.k = -1;
+    p.i = p.j = 0;
+    p.acc = R(0);
+    Stream st(d.key0, d.key1, s, (uint32_t)c, 0u, kTagColl);
+    for (;;) {
+        const bool idle = p.k < 0;
+        const unsigned long long im = __ballot(idle);
+        if (idle) {
+            const int64_t k = next + __popcll(im & lt);
+            if (k < M) draw_candidate<R>(d, s, c, nc, k, p, st);
+        }
+        next += __popcll(im);
+        const bool active = p.k >= 0;
+        if (__ballot(active) == 0ull) break;
+        const int hi = p.i & (kClaimTable - 1), hj = p.j & (kClaimTable - 1);
+        if (active) {
+            atomicMin(&tab[hi], (uint32_t)p.k);
+            atomicMin(&tab[hj], (uint32_t)p.k);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const bool win = active && tab[hi] == (uint32_t)p.k && tab[hj] == (uint32_t)p.k;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (active) {
+            tab[hi] = 0xFFFFFFFFu;
+            tab[hj] = 0xFFFFFFFFu;
+        }
+        if (win) run_candidate<R>(p, st, crmr, vx, vy, vz, o, lane_max, lane_coll);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    double mx = (double)lane_max;
+    uint32_t cc = lane_coll;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double other = __shfl_xor(mx, off, 64);
+        mx = other > mx ? other : mx;
+        cc += __shfl_xor(cc, off, 64);
+    }
+    if (lane == 0) {
+        d.rem[c] = mreal - mf;
+        if (mx > crm0) d.crmax[c] = mx;
+        d.ncoll[c] += cc;
+    }
+}
+
+struct CoopShared {
+    int idle[kFastWaves];
+    double mx[kFastWaves];
+    uint32_t coll[kFastWaves];
+    double mom[kFastWaves][kMoments];
+};
+
+// NTC of one cell by the whole workgroup (rounds of blockDim candidates).
+// Every thread of the workgroup must call it.
+template <class R>
+__device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, R* vx, R* vy,
+                         R* vz, uint32_t* tab, CoopShared& sh) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const unsigned long long lt = lanes_below(lane);
+    const double crm0 = d.crmax[c];
+    const double mreal = (((0.5 * (double)nc) * (double)(nc - 1)) * crm0) * d.kntc + d.rem[c];
+    const double mf = floor(mreal);
+    const int64_t M = (int64_t)mf;
+    const R crmr = (R)crm0;
+    R lane_max = R(0);
+    uint32_t lane_coll = 0;
+    int64_t next = 0;
+    Pend<R> p;
+    p.k = -1;
+    p.i = p.j = 0;
+    p.acc = R(0);
+    Stream st(d.key0, d.key1, s, (uint32_t)c, 0u, kTagColl);
+    for (;;) {
+        const bool idle = p.k < 0;
+        const unsigned long long im = __ballot(idle);
+        if (lane == 0) sh.idle[wv] = __popcll(im);
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int q = 0; q < nw; ++q) {
+            const int v = sh.idle[q];
+            off += q < wv ? v : 0;
+            tot += v;
+        }
+        if (idle) {
+            const int64_t k = next + off + __popcll(im & lt);
+            if (k < M) draw_candidate<R>(d, s, c, nc, k, p, st);
+        }
+        next += tot;
+        const bool active = p.k >= 0;
+        if (!__syncthreads_or(active)) break;
+        const int hi = p.i & (kCoopTable - 1), hj = p.j & (kCoopTable - 1);
+        if (active) {
+            atomicMin(&tab[hi], (uint32_t)p.k);
+            atomicMin(&tab[hj], (uint32_t)p.k);
+        }
+        __syncthreads();
+        const bool win = active && tab[hi] == (uint32_t)p.k && tab[hj] == (uint32_t)p.k;
+        __syncthreads();
+        if (active) {
+            tab[hi] = 0xFFFFFFFFu;
+            tab[hj] = 0xFFFFFFFFu;
+        }
+        if (win) run_candidate<R>(p, st, crmr, vx, vy, vz, o, lane_max, lane_coll);
+    }
+    double mx = (double)lane_max;
+    uint32_t cc = lane_coll;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double other = __shfl_xor(mx, off, 64);
+        mx = other > mx ? other : mx;
+        cc += __shfl_xor(cc, off, 64);
+    }
+    if (lane == 0) {
+        sh.mx[wv] = mx;
+        sh.coll[wv] = cc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh.mx[0];
+        uint32_t t = sh.coll[0];
+        for (int q = 1; q < nw; ++q) {
+            m = sh.mx[q] > m ? sh.mx[q] : m;
+            t += sh.coll[q];
+        }
+        d.rem[c] = mreal - mf;
+        if (m > crm0) d.crmax[c] = m;
+        d.ncoll[c] += t;
+    }
+    __syncthreads();
+}
+
+// Sampling sums of one cell: per lane over a strided share of the cell, then
+// a fixed butterfly over the wavefront (and, in workgroup mode, the wavefront
+// partials added in wavefront order).
+template <class R>
+__device__ __forceinline__ void cell_moments(const R* vx, const R* vy, const R* vz, int o, int nc,
+                                             int first, int stride, double tot[kMoments]) {
+    Mom m;
+    mom_zero(m);
+    for (int q = first; q < nc; q += stride)
+        mom_add(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
+#pragma unroll
+    for (int k = 0; k < kMoments; ++k) tot[k] = wave_sum_fixed(m.s[k]);
+}
+
 template <class R>
 __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc* __restrict__ descs,
                                                                  const int4* __restrict__ work,
                                                                  int cap, int do_collide) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ CoopShared sh;
     const int nw = blockDim.x >> 6;
     uint32_t* claims = (uint32_t*)smem;
-    R* lds_v = (R*)(claims + nw * kClaimTable);
+    R* lds_v = (R*)(claims + kCoopTable);
     const int4 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
     const int c0 = w.y, c1 = w.z;
@@ -537,109 +749,44 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
         vy = g.vy + s0;
         vz = g.vz + s0;
     }
-    for (int i = threadIdx.x; i < nw * kClaimTable; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
+    for (int i = threadIdx.x; i < kCoopTable; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long lt = lanes_below(lane);
-    uint32_t* tab = claims + wv * kClaimTable;
-    for (int c = c0 + wv; c < c1; c += nw) {
+    // cells of at least kCoopMin particles: one at a time, whole workgroup
+    for (int c = c0; c < c1; ++c) {
         const int nc = d.count[c];
+        if (nc < kCoopMin) continue;
         const int o = d.offset[c] - s0;
-        if (do_collide && nc >= 2) {
-            const double crm0 = d.crmax[c];
-            const double mreal = (((0.5 * (double)nc) * (double)(nc - 1)) * crm0) * d.kntc + d.rem[c];
-            const double mf = floor(mreal);
-            if (lane == 0) d.rem[c] = mreal - mf;
-            const int64_t M = (int64_t)mf;
-            const R crmr = (R)crm0;
-            R lane_max = R(0);
-            uint32_t lane_coll = 0;
-            int64_t next = 0;
-            int64_t myk = -1;
-            int mi = 0, mj = 0;
-            R macc = R(0);
-            Stream st(d.key0, d.key1, (uint32_t)s, (uint32_t)c, 0u, kTagColl);
-            for (;;) {
-                const bool idle = myk < 0;
-                const unsigned long long idle_mask = __ballot(idle);
-                if (idle) {
-                    const int64_t k = next + __popcll(idle_mask & lt);
-                    if (k < M) {
-                        myk = k;
-                        st = Stream(d.key0, d.key1, (uint32_t)s, (uint32_t)c, (uint32_t)k, kTagColl);
-                        R ua, ub;
-                        Cand<R>::draw(st, ua, ub, macc);
-                        mi = min((int)(ua * (R)nc), nc - 1);
-                        mj = min((int)(ub * (R)(nc - 1)), nc - 2);
-                        if (mj >= mi) ++mj;
-                    }
-                }
-                next += __popcll(idle_mask);
-                const bool active = myk >= 0;
-                if (__ballot(active) == 0ull) break;
-                const int hi = mi & (kClaimTable - 1), hj = mj & (kClaimTable - 1);
-                if (active) {
-                    atomicMin(&tab[hi], (uint32_t)myk);
-                    atomicMin(&tab[hj], (uint32_t)myk);
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                const bool win = active && tab[hi] == (uint32_t)myk && tab[hj] == (uint32_t)myk;
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                if (active) {
-                    tab[hi] = 0xFFFFFFFFu;
-                    tab[hj] = 0xFFFFFFFFu;
-                }
-                if (win) {
-                    const int i = o + mi, j = o + mj;
-                    const R xi = vx[i], yi = vy[i], zi = vz[i];
-                    const R xj = vx[j], yj = vy[j], zj = vz[j];
-                    const R crx = xi - xj, cry = yi - yj, crz = zi - zj;
-                    const R cr = Num<R>::sqrt((crx * crx + cry * cry) + crz * crz);
-                    lane_max = cr > lane_max ? cr : lane_max;
-                    const R cm = cr > crmr ? cr : crmr;
-                    if (macc * cm < cr) {
-                        R dx, dy, dz;
-                        sphere_point<R>(st, dx, dy, dz);
-                        const R cmx = R(0.5) * (xi + xj), cmy = R(0.5) * (yi + yj),
-                                cmz = R(0.5) * (zi + zj);
-                        const R hh = R(0.5) * cr;
-                        vx[i] = cmx + hh * dx;
-                        vy[i] = cmy + hh * dy;
-                        vz[i] = cmz + hh * dz;
-                        vx[j] = cmx - hh * dx;
-                        vy[j] = cmy - hh * dy;
-                        vz[j] = cmz - hh * dz;
-                        ++lane_coll;
-                    }
-                    myk = -1;
-                }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            }
-            double mx = (double)lane_max;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double other = __shfl_xor(mx, off, 64);
-                mx = other > mx ? other : mx;
-            }
-            uint32_t cc = lane_coll;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) cc += __shfl_xor(cc, off, 64);
-            if (lane == 0) {
-                if (mx > crm0) d.crmax[c] = mx;
-                d.ncoll[c] += cc;
-            }
-        }
+        if (do_collide) coop_ntc<R>(d, (uint32_t)s, c, nc, o, vx, vy, vz, claims, sh);
         if (sample) {
-            Mom m;
-            mom_zero(m);
-            for (int q = lane; q < nc; q += 64)
-                mom_add(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
             double tot[kMoments];
-#pragma unroll
-            for (int k = 0; k < kMoments; ++k) tot[k] = wave_sum_fixed(m.s[k]);
+            cell_moments<R>(vx, vy, vz, o, nc, (int)threadIdx.x, (int)blockDim.x, tot);
+            if (lane == 0)
+                for (int k = 0; k < kMoments; ++k) sh.mom[wv][k] = tot[k];
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double* a = d.acc + (size_t)c * kMoments;
+                for (int k = 0; k < kMoments; ++k) {
+                    double t = sh.mom[0][k];
+                    for (int q = 1; q < nw; ++q) t += sh.mom[q][k];
+                    a[k] += t;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // smaller cells: one wavefront each
+    uint32_t* tab = claims + wv * kClaimTable;
+    int rank = 0;
+    for (int c = c0; c < c1; ++c) {
+        const int nc = d.count[c];
+        if (nc >= kCoopMin) continue;
+        if ((rank++ % nw) != wv) continue;
+        const int o = d.offset[c] - s0;
+        if (do_collide && nc >= 2) wave_ntc<R>(d, (uint32_t)s, c, nc, o, vx, vy, vz, tab);
+        if (sample) {
+            double tot[kMoments];
+            cell_moments<R>(vx, vy, vz, o, nc, lane, 64, tot);
             if (lane == 0) {
                 double* a = d.acc + (size_t)c * kMoments;
 #pragma unroll
@@ -750,8 +897,8 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
         mark(3);
         hipLaunchKernelGGL(k_colprefix, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
         mark(4);
-        hipLaunchKernelGGL((k_scatter<R>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds, st,
-                           w.desc, w.tiles);
+        hipLaunchKernelGGL((k_scatter<R>), dim3(w.n_tiles), dim3(kParticleThreads),
+                           hist_lds * kScatterWaves, st, w.desc, w.tiles);
     } else {
         mark(2);
         hipLaunchKernelGGL(k_scan, dim3(w.n_inst), dim3(kScanThreads), 0, st, w.desc, 0);
@@ -779,7 +926,7 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
 
 size_t fast_collide_lds_bytes(Mode mode, int cap) {
     const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
-    return (size_t)kFastWaves * kClaimTable * sizeof(uint32_t) + 3 * (size_t)cap * rb;
+    return (size_t)kCoopTable * sizeof(uint32_t) + 3 * (size_t)cap * rb;
 }
 
 void launch_init(const InstDesc& d, const InstDesc* d_desc, Mode mode, hipStream_t s) {

@@ -39,6 +39,8 @@ int fail(std::string* sink, int code, const std::string& msg) {
     } while (0)
 
 constexpr uint64_t kAlign = 256;
+// four LDS tables of this many cells fill 160 KiB of LDS
+constexpr int64_t kMaxCollisionCells = 10240;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Derived sizes and constants of one instance (the same for footprint and
@@ -56,8 +58,8 @@ struct Plan {
 };
 
 int base_items_per_thread(int32_t N, int32_t Cc) {
-    // Tiles of 256 * k slots with at least 4 slots per collision cell keep the
-    // per-tile histogram traffic near one byte per particle.
+    // Tiles of 256 * k slots with at least 4 slots per collision cell keep
+    // the per-tile histogram traffic near one byte per particle.
     int k = (int)std::ceil(4.0 * (double)Cc / (double)kParticleThreads);
     k = std::max(1, std::min(64, k));
     const int64_t need = (int64_t)((N + kParticleThreads - 1) / kParticleThreads);
@@ -81,8 +83,8 @@ int check_params(const dsmc_params* p, std::string* err) {
         return fail(err, DSMC_ERR_INVALID_ARG, "n_cells, particles_per_cell and n_sub must be >= 1");
     if ((int64_t)p->n_cells * p->particles_per_cell > (int64_t)INT32_MAX / 2)
         return fail(err, DSMC_ERR_INVALID_ARG, "too many particles for int32 slots");
-    if ((int64_t)p->n_cells * p->n_sub > 65536)
-        return fail(err, DSMC_ERR_INVALID_ARG, "n_cells * n_sub exceeds 65536 collision cells");
+    if ((int64_t)p->n_cells * p->n_sub > kMaxCollisionCells)
+        return fail(err, DSMC_ERR_INVALID_ARG, "n_cells * n_sub exceeds the collision-cell limit");
     if (p->n_transient < 0) return fail(err, DSMC_ERR_INVALID_ARG, "n_transient must be >= 0");
     if (p->debug_phase_mask > DSMC_PHASE_ALL) return fail(err, DSMC_ERR_INVALID_ARG, "bad phase mask");
     return DSMC_OK;
@@ -227,10 +229,13 @@ void drop_graph(dsmc_group* g) {
 }
 
 int auto_cpb(const dsmc_handle* h) {
-    // Aim at about 2048 particles per fast-collide workgroup, at least one cell.
+    // Cells of kCoopMin or more particles get a workgroup each; smaller ones
+    // are packed about 2048 particles (and at least one cell per wavefront)
+    // to a workgroup.
     const double per_cell = (double)h->plan.N / (double)h->plan.Cc;
-    int c = (int)std::floor(2048.0 / std::max(per_cell, 1.0));
-    return std::max(1, std::min(c, 64));
+    if (per_cell >= kCoopMin) return 1;
+    const int c = (int)std::floor(2048.0 / std::max(per_cell, 1.0));
+    return std::max(kFastWaves, std::min(c, 64));
 }
 
 // (Re)build the device work lists and launch shapes of a group.
@@ -264,19 +269,21 @@ int rebuild(dsmc_group* g) {
         } else {
             const int cpb = g->cpb > 0 ? g->cpb : auto_cpb(h);
             for (int c = 0; c < d.Cc; c += cpb) cblocks.push_back(make_int4(i, c, std::min(c + cpb, d.Cc), 0));
-            const double per_cell = (double)d.N / (double)d.Cc;
-            const int want = (int)std::ceil(1.25 * per_cell * cpb + 8.0 * std::sqrt(per_cell * cpb) + 64.0);
+            // staging room for a block's particles: mean + 6 Poisson sigma
+            // (a fuller block works on global memory instead)
+            const double per_block = (double)d.N / (double)d.Cc * cpb;
+            const int want = (int)std::ceil(per_block + 6.0 * std::sqrt(per_block) + 64.0);
             cap = std::max(cap, want);
         }
     }
     // fit the fast-collide staging area into the device's LDS
     const size_t rb = g->mode == kFp32Fast ? 4 : 8;
     const int max_lds = device_max_lds();
-    const size_t fixed = (size_t)kFastWaves * kClaimTable * 4;
+    const size_t fixed = (size_t)kCoopTable * 4 + 1024;  // claim table + static shared
     const int cap_max = (int)(((size_t)max_lds - fixed) / (3 * rb));
     cap = std::min(cap, cap_max);
-    if ((size_t)max_cc * 4 > (size_t)max_lds)
-        return fail(&g->err, DSMC_ERR_INVALID_ARG, "collision cells exceed the LDS histogram");
+    if ((size_t)max_cc * 4 * kScatterWaves > (size_t)max_lds)
+        return fail(&g->err, DSMC_ERR_INVALID_ARG, "collision cells exceed the LDS tables of the scatter");
 
     const size_t need = align_up(sizeof(InstDesc) * std::max(n, 1)) + align_up(sizeof(int2) * std::max<size_t>(tiles.size(), 1)) +
                         align_up(sizeof(int4) * std::max<size_t>(cols.size(), 1)) +
