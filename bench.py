@@ -48,6 +48,34 @@ def kernel_bytes(phase: str, N: int, Cc: int, rb: int, coll_frac: float, samplin
     return 0.0
 
 
+PROFILE_TAGS = {"cfg1": "kernels_cfg1_kn0.1_300x1000_fp32"}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "rng.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2311_14140_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """Copy-calibrated HBM bytes per launch of a kernel from the committed
+    rocprofv3 counter summary, or None when there is none or the kernels have
+    changed since the counters were taken."""
+    import json as _json
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    tag = PROFILE_TAGS.get(workload)
+    if not tag or not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = _json.load(fh).get(tag)
+    if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec["bytes_per_launch"].get(kernel)
+
+
 def cpu_oracle_rate(params, seconds: float):
     import oracle
     o = oracle.Oracle(params)
@@ -62,6 +90,55 @@ def cpu_oracle_rate(params, seconds: float):
     return o.N * steps / el, steps, el
 
 
+def _timed(torch, step, sync, n):
+    sync()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    step(n)
+    sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+def time_single(dsmc, torch, p, steps):
+    """particle-steps/s of one instance (sampling steps, graph-replayed)."""
+    p = p.with_(n_transient=4)
+    with dsmc.Solver(p) as s:
+        s.step(8)
+        el = _timed(torch, s.step, s.sync, steps)
+        prof = s.profile(4)
+        return {"value": s.N * steps / el, "unit": "particle-steps/s", "particles": s.N,
+                "steps": steps, "ms_per_step": 1e3 * el / steps,
+                "workload": f"Kn={p.kn}, F={p.body_force}, {p.n_cells} cells x "
+                            f"{p.particles_per_cell}/cell, n_sub={p.n_sub}, FP32",
+                "kernel_ms_per_step": {k: prof[k] / 4 for k in dsmc.Solver.PHASES}}
+
+
+def time_batched(dsmc, torch, steps):
+    """particle-steps/s of the 256-instance mix stepped as one group."""
+    import synth
+    ps = synth.config3_instances(256)
+    g = dsmc.Group()
+    sols = []
+    for p in ps:
+        s = dsmc.Solver(p.with_(n_transient=4))
+        g.add(s)
+        sols.append(s)
+    N = sum(s.N for s in sols)
+    g.step(8)
+    el = _timed(torch, g.step, g.sync, steps)
+    prof = sols[0].profile(4)
+    out = {"value": N * steps / el, "unit": "particle-steps/s", "particles": N,
+           "instances": len(sols), "steps": steps, "ms_per_step": 1e3 * el / steps,
+           "workload": "256 instances: Kn log-uniform [0.05, 10], F uniform [0.001, 0.02], "
+                       "cells uniform [50, 2000], particles/cell uniform [20, 200], FP32",
+           "kernel_ms_per_step": {k: prof[k] / 4 for k in dsmc.Solver.PHASES}}
+    g.close()
+    for s in sols:
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +149,12 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the large-instance and batched-mix measurements")
+    ap.add_argument("--extra-steps", type=int, default=20)
+    ap.add_argument("--copy-mib", type=int, default=256,
+                    help="size of the plain device copy run after the timed region, whose "
+                         "HBM counters calibrate the kernels' (0 = skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -139,6 +222,24 @@ def main():
                 "steps": args.fp64_steps, "dtype": "f64",
                 "note": "sequential-per-cell NTC, bit-identical to the oracle"}
 
+    # ---- other workloads of the same hot path, timed the same way
+    extra = {}
+    if not args.no_extra:
+        extra["cfg2_large_instance"] = time_single(dsmc, torch, WORKLOADS["cfg2"][0].with_(
+            n_sub=2), args.extra_steps)
+        extra["cfg3_batched_256"] = time_batched(dsmc, torch, args.extra_steps)
+
+    # a plain copy of known size (outside the timed region): what the
+    # FETCH_SIZE / WRITE_SIZE counters read for it calibrates the kernels'
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     cpu = None
     if not args.no_cpu_baseline:
         cq = base.with_(precision=FP64_DETERMINISTIC)
@@ -167,7 +268,7 @@ def main():
                    "collision_cells": Cc, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "kernel_ms": kern[dom],
+                     "traffic": measured_traffic(args.workload, dom), "kernel_ms": kern[dom],
                      "algorithmic_bytes_per_launch": dom_bytes},
         "step_roofline": {"algorithmic_bytes_per_step": step_bytes,
                           "achieved_GBps": step_bytes / (el / args.steps) / 1e9,
@@ -176,6 +277,7 @@ def main():
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
         "mass_flow": est["mass_flow"],
+        "other_workloads": extra,
     }
     print(json.dumps(line), flush=True)
 

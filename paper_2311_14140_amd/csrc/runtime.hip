@@ -697,24 +697,30 @@ int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
         const int r = rebuild(g);
         if (r) return r;
     }
-    hipEvent_t ev[7];
-    for (int i = 0; i < 7; ++i) HIP_TRY(&h->err, hipEventCreate(&ev[i]));
+    // all steps are enqueued before any wait, so the device runs them back to
+    // back and the events bracket kernel execution, not host launch gaps
+    std::vector<hipEvent_t> ev((size_t)n_steps * 7, nullptr);
+    int rc = DSMC_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) rc = fail(&h->err, DSMC_ERR_DEVICE, "hipEventCreate failed");
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const auto t0 = std::chrono::steady_clock::now();
-    int rc = DSMC_OK;
-    for (int64_t k = 0; k < n_steps && rc == DSMC_OK; ++k) {
-        launch_step_timed(g->work, (Mode)g->mode, g->phase, g->stream, ev);
-        if (hipEventSynchronize(ev[6]) != hipSuccess) {
+    if (rc == DSMC_OK) {
+        for (int64_t k = 0; k < n_steps; ++k)
+            launch_step_timed(g->work, (Mode)g->mode, g->phase, g->stream, ev.data() + 7 * k);
+        if (hipEventSynchronize(ev.back()) != hipSuccess)
             rc = fail(&h->err, DSMC_ERR_DEVICE, "event synchronise failed");
-            break;
-        }
-        for (int i = 0; i < 6; ++i) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) acc[i] += ms;
-        }
     }
     const auto t1 = std::chrono::steady_clock::now();
-    for (int i = 0; i < 7; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc == DSMC_OK) {
+        for (int64_t k = 0; k < n_steps; ++k)
+            for (int i = 0; i < 6; ++i) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[7 * k + i], ev[7 * k + i + 1]) == hipSuccess) acc[i] += ms;
+            }
+    }
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
     if (rc) return rc;
     if (g->phase & DSMC_PHASE_SORT) {
         if (g->solo) h->sorted = true;
