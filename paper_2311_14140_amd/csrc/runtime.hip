@@ -200,7 +200,7 @@ struct dsmc_group {
     std::vector<dsmc_handle*> members;
     bool dirty = true;
     int tile_mult = 0;   // 0 = automatic
-    int cpb = 0;         // 0 = automatic
+    int ppb = 0;         // target particles per fast-collide workgroup, 0 = automatic
     // device-side work lists
     void* d_mem = nullptr;
     size_t d_bytes = 0;
@@ -228,14 +228,15 @@ void drop_graph(dsmc_group* g) {
     g->graph = nullptr;
 }
 
-int auto_cpb(const dsmc_handle* h) {
+int auto_cpb(const dsmc_handle* h, int target_particles) {
     // Cells of kCoopMin or more particles get a workgroup each; smaller ones
-    // are packed about 2048 particles (and at least one cell per wavefront)
+    // are packed about target_particles (and at least one cell per wavefront)
     // to a workgroup.
     const double per_cell = (double)h->plan.N / (double)h->plan.Cc;
     if (per_cell >= kCoopMin) return 1;
-    const int c = (int)std::floor(2048.0 / std::max(per_cell, 1.0));
-    return std::max(kFastWaves, std::min(c, 64));
+    const double target = target_particles > 0 ? (double)target_particles : 2048.0;
+    const int c = (int)std::floor(target / std::max(per_cell, 1.0));
+    return std::max(kFastWaves, std::min(c, 256));
 }
 
 // (Re)build the device work lists and launch shapes of a group.
@@ -267,7 +268,7 @@ int rebuild(dsmc_group* g) {
         if (g->mode == kFp64Det) {
             for (int c = 0; c < d.Cc; c += 64) cblocks.push_back(make_int4(i, c, std::min(c + 64, d.Cc), 0));
         } else {
-            const int cpb = g->cpb > 0 ? g->cpb : auto_cpb(h);
+            const int cpb = auto_cpb(h, g->ppb);
             for (int c = 0; c < d.Cc; c += cpb) cblocks.push_back(make_int4(i, c, std::min(c + cpb, d.Cc), 0));
             // staging room for a block's particles: mean + 6 Poisson sigma
             // (a fuller block works on global memory instead)
@@ -800,21 +801,133 @@ int dsmc_group_destroy(dsmc_group* g) {
     return DSMC_OK;
 }
 
-int dsmc_group_set_tuning(dsmc_group* g, int32_t tile_mult, int32_t cells_per_block) {
+int dsmc_group_set_tuning(dsmc_group* g, int32_t tile_mult, int32_t particles_per_block) {
     if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
-    if (tile_mult < 0 || tile_mult > 64 || cells_per_block < 0 || cells_per_block > 1024)
+    if (tile_mult < 0 || tile_mult > 16 || particles_per_block < 0 || particles_per_block > (1 << 20))
         return fail(&g->err, DSMC_ERR_INVALID_ARG, "tuning out of range");
     g->tile_mult = tile_mult;
-    g->cpb = cells_per_block;
+    g->ppb = particles_per_block;
     g->dirty = true;
     return DSMC_OK;
 }
 
-int dsmc_group_autotune(dsmc_group* g, int32_t* tile_mult_out, int32_t* cpb_out) {
+}  // extern "C"
+
+namespace {
+
+std::mutex g_tune_mu;
+std::vector<std::pair<std::string, std::pair<int, int>>> g_tune_cache;
+
+// Signature of a group's launch problem: precision and the (N, Cc) of every
+// member, so groups of the same shape reuse a tuning.
+std::string group_signature(const dsmc_group* g) {
+    std::vector<std::pair<int, int>> v;
+    for (const dsmc_handle* h : g->members) v.emplace_back(h->plan.N, h->plan.Cc);
+    std::sort(v.begin(), v.end());
+    std::string s = std::to_string(g->mode);
+    uint64_t hsh = 1469598103934665603ull;
+    for (auto& e : v) {
+        hsh = (hsh ^ (uint64_t)e.first) * 1099511628211ull;
+        hsh = (hsh ^ (uint64_t)e.second) * 1099511628211ull;
+    }
+    return s + ":" + std::to_string(v.size()) + ":" + std::to_string(hsh);
+}
+
+bool tune_lookup(const std::string& sig, int* tm, int* ppb) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (auto& e : g_tune_cache)
+        if (e.first == sig) {
+            *tm = e.second.first;
+            *ppb = e.second.second;
+            return true;
+        }
+    const char* path = std::getenv("DSMC_AUTOTUNE_CACHE");
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char key[256];
+    int a, b;
+    bool found = false;
+    while (std::fscanf(f, "%255s %d %d", key, &a, &b) == 3)
+        if (sig == key) {
+            *tm = a;
+            *ppb = b;
+            found = true;
+        }
+    std::fclose(f);
+    if (found) g_tune_cache.push_back({sig, {*tm, *ppb}});
+    return found;
+}
+
+void tune_store(const std::string& sig, int tm, int ppb) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.push_back({sig, {tm, ppb}});
+    const char* path = std::getenv("DSMC_AUTOTUNE_CACHE");
+    if (!path) return;
+    if (FILE* f = std::fopen(path, "a")) {
+        std::fprintf(f, "%s %d %d\n", sig.c_str(), tm, ppb);
+        std::fclose(f);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+// Tries every (tile multiplier, particles per collide workgroup) pair on the
+// group's own steps (3 timed steps each after one untimed step, HIP events on
+// the group's stream) and keeps the fastest.  Results do not depend on the
+// launch shape, so these are ordinary steps of the members.
+int dsmc_group_autotune(dsmc_group* g, int32_t* tile_mult_out, int32_t* ppb_out) {
     if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
-    (void)tile_mult_out;
-    (void)cpb_out;
-    return fail(&g->err, DSMC_ERR_STATE, "autotuning not available yet");
+    if (g->members.empty()) return fail(&g->err, DSMC_ERR_STATE, "group has no members");
+    const std::string sig = group_signature(g);
+    int best_tm = 1, best_ppb = 2048;
+    if (!tune_lookup(sig, &best_tm, &best_ppb)) {
+        static const int tms[] = {1, 2, 4};
+        static const int ppbs[] = {1024, 2048, 4096};
+        hipEvent_t e0, e1;
+        HIP_TRY(&g->err, hipEventCreate(&e0));
+        HIP_TRY(&g->err, hipEventCreate(&e1));
+        float best = 1e30f;
+        int rc = DSMC_OK;
+        for (int tm : tms) {
+            for (int pb : ppbs) {
+                g->tile_mult = tm;
+                g->ppb = pb;
+                g->dirty = true;
+                rc = enqueue_steps(g, 1);
+                if (rc) break;
+                (void)hipEventRecord(e0, g->stream);
+                rc = enqueue_steps(g, 3);
+                if (rc) break;
+                (void)hipEventRecord(e1, g->stream);
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    rc = fail(&g->err, DSMC_ERR_DEVICE, "event synchronise failed");
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) {
+                    best = ms;
+                    best_tm = tm;
+                    best_ppb = pb;
+                }
+            }
+            if (rc) break;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        for (dsmc_handle* h : g->members) h->sorted = true;
+        if (rc) return rc;
+        tune_store(sig, best_tm, best_ppb);
+    }
+    g->tile_mult = best_tm;
+    g->ppb = best_ppb;
+    g->dirty = true;
+    if (tile_mult_out) *tile_mult_out = best_tm;
+    if (ppb_out) *ppb_out = best_ppb;
+    return DSMC_OK;
 }
 
 }  // extern "C"

@@ -308,8 +308,8 @@ class Group:
     def sync(self):
         _check(lib.dsmc_group_sync(self._g))
 
-    def set_tuning(self, tile_mult: int = 0, cells_per_block: int = 0):
-        _check(lib.dsmc_group_set_tuning(self._g, int(tile_mult), int(cells_per_block)))
+    def set_tuning(self, tile_mult: int = 0, particles_per_block: int = 0):
+        _check(lib.dsmc_group_set_tuning(self._g, int(tile_mult), int(particles_per_block)))
 
     def autotune(self):
         a, b = ct.c_int32(), ct.c_int32()

@@ -172,12 +172,12 @@ def test_instance_alone_equals_in_group(D, prec_name):
 def test_launch_shape_does_not_change_results(D):
     ps = _mix(D, D.DSMC_FP32_FAST)
     results = []
-    for tile_mult, cpb in ((0, 0), (2, 1), (4, 7)):
+    for tile_mult, ppb in ((0, 0), (2, 256), (4, 8192)):
         g = D.Group()
         sols = [D.Solver(p) for p in ps]
         for s in sols:
             g.add(s)
-        g.set_tuning(tile_mult, cpb)
+        g.set_tuning(tile_mult, ppb)
         g.step(17)
         g.sync()
         results.append([s.get_state() for s in sols])
@@ -217,6 +217,28 @@ def test_group_membership_changes(D):
     g.remove(sols[3])
     sols[3].step(10)          # s3 alone: 30
     g.step(0)
+    for s, r in zip(sols, ref):
+        for a, b in zip(s.get_state(), r):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+    g.close()
+
+
+def test_autotune_choice_valid_and_results_unchanged(D):
+    ps = _mix(D, D.DSMC_FP32_FAST)
+    ref = []
+    for p in ps:
+        with D.Solver(p) as s:
+            s.step(40)
+            ref.append(s.get_state())
+    g = D.Group()
+    sols = [D.Solver(p) for p in ps]
+    for s in sols:
+        g.add(s)
+    tm, ppb = g.autotune()          # runs 36 real steps
+    assert tm in (1, 2, 4) and ppb in (1024, 2048, 4096)
+    assert g.autotune() == (tm, ppb)  # cached per group shape: no further steps
+    g.step(4)
+    g.sync()
     for s, r in zip(sols, ref):
         for a, b in zip(s.get_state(), r):
             assert np.array_equal(np.asarray(a), np.asarray(b))
