@@ -198,13 +198,14 @@ int dsmc_group_destroy(dsmc_group *g);
 
 /* Launch-shape tuning of a group: tile_mult multiplies each member's base
  * particle tile (the slots one move or scatter workgroup walks; 1..16) and
- * particles_per_block is the number of particles a fast-collide workgroup
- * aims to stage on chip (cells are packed up to it; cells of 256 or more
- * particles always get a workgroup each); 0 keeps the automatic choice
- * (1, 2048).  Results do not depend on either. */
+ * particles_per_block packs that many particles' worth of collision cells
+ * into one workgroup of the LDS-staged collide (instances with 256 or more
+ * particles per collision cell; the workgroup takes its cells one after
+ * another); 0 keeps the automatic choice (1, one cell per workgroup).
+ * Results do not depend on either. */
 int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t particles_per_block);
 /* Time every pair of tile_mult in {1, 2, 4} and particles_per_block in
- * {1024, 2048, 4096} on the group's own steps (4 steps each; they are real
+ * {0, 2048, 4096} on the group's own steps (4 steps each; they are real
  * steps of the members) and keep the fastest.  The choice is cached per group
  * shape (precision and the particles and collision cells of every member), in
  * the process and, if DSMC_AUTOTUNE_CACHE names a file, across processes.

@@ -15,6 +15,7 @@ constexpr int kSegTiles = 32;          // tiles per column-scan segment
 constexpr int kClaimTable = 1024;      // per-wavefront claim table of the fast collide
 constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
 constexpr int kCoopMin = 256;          // cells this full are collided by a whole workgroup
+constexpr int kGroupTableFactor = 16;  // claim-table entries per lane of a small-cell group
 constexpr int kCoopTable = kFastWaves * kClaimTable;  // its claim table (the wave tables together)
 
 // Scalars an instance keeps on the device so that a step is the same launch

@@ -30,15 +30,27 @@ namespace {
 
 constexpr unsigned kPhaseMove = 1, kPhaseSort = 2, kPhaseCollide = 4, kPhaseSample = 8;
 
+// Device arrays reached through the descriptor are generic pointers; typed
+// into the global address space, their accesses become global_* rather than
+// flat_* instructions (flat accesses also wait on the LDS counter and cannot
+// use scalar base addresses).
+template <class T> struct GlobalSpace {
+    typedef __attribute__((address_space(1))) T type;
+};
+template <class T> using gptr = typename GlobalSpace<T>::type*;
+template <class T> __device__ __forceinline__ gptr<T> gmem(void* p) { return (gptr<T>)p; }
+template <class T> __device__ __forceinline__ gptr<T> gmem(T* p) { return (gptr<T>)p; }
+
 template <class R> struct P4 {
-    R* y;
-    R* vx;
-    R* vy;
-    R* vz;
+    gptr<R> y;
+    gptr<R> vx;
+    gptr<R> vy;
+    gptr<R> vz;
 };
 
 template <class R> __device__ __forceinline__ P4<R> particles(const InstDesc& d, int b) {
-    return P4<R>{(R*)d.buf[b][0], (R*)d.buf[b][1], (R*)d.buf[b][2], (R*)d.buf[b][3]};
+    return P4<R>{gmem<R>(d.buf[b][0]), gmem<R>(d.buf[b][1]), gmem<R>(d.buf[b][2]),
+                 gmem<R>(d.buf[b][3])};
 }
 
 __device__ __forceinline__ unsigned long long lanes_below(int lane) {
@@ -149,6 +161,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* 
     const P4<R> b = particles<R>(d, (int)((s - 1) & 1));
     const int start = w.y * d.tile_items;
     const int end = min(start + d.tile_items, d.N);
+    const gptr<int32_t> cellp = gmem(d.cell);
     int bad = 0;
     for (int p = start + (int)threadIdx.x; p < end; p += blockDim.x) {
         int c;
@@ -163,15 +176,15 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* 
             }
             bad |= !(isfinite(vx) && isfinite(vy) && isfinite(vz));
             c = cell_of<R>(d, y);
-            d.cell[p] = c;
+            cellp[p] = c;
         } else {
-            c = d.cell[p];
+            c = cellp[p];
         }
         atomicAdd(&hist[c], 1);
     }
     if (kMove && bad) atomicOr(&blk_bad, 1);
     __syncthreads();
-    int* row = d.counts + (size_t)w.y * Cc;
+    const gptr<int32_t> row = gmem(d.counts) + (size_t)w.y * Cc;
     for (int c = threadIdx.x; c < Cc; c += blockDim.x) row[c] = hist[c];
     // error path only: a non-finite velocity was seen in this tile
     if (kMove && threadIdx.x == 0 && blk_bad) atomicOr(&d.sc->status, 1);
@@ -189,8 +202,9 @@ __global__ __launch_bounds__(kColThreads) void k_colsum(const InstDesc* __restri
     const int c = w.y * kColThreads + (int)threadIdx.x;
     if (c >= d.Cc) return;
     const int t0 = w.z * kSegTiles, t1 = min(t0 + kSegTiles, d.tiles);
+    const gptr<int32_t> cnt = gmem(d.counts);
     int sum = 0;
-    for (int t = t0; t < t1; ++t) sum += d.counts[(size_t)t * d.Cc + c];
+    for (int t = t0; t < t1; ++t) sum += cnt[(size_t)t * d.Cc + c];
     d.segsum[(size_t)w.z * d.Cc + c] = sum;
 }
 
@@ -261,8 +275,9 @@ __global__ __launch_bounds__(kColThreads) void k_colprefix(const InstDesc* __res
     if (c >= d.Cc) return;
     const int t0 = w.z * kSegTiles, t1 = min(t0 + kSegTiles, d.tiles);
     int run = d.segsum[(size_t)w.z * d.Cc + c];
+    const gptr<int32_t> cnt = gmem(d.counts);
     for (int t = t0; t < t1; ++t) {
-        int* e = d.counts + (size_t)t * d.Cc + c;
+        const gptr<int32_t> e = cnt + (size_t)t * d.Cc + c;
         const int v = *e;
         *e = run;
         run += v;
@@ -299,10 +314,11 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
     const int quarter = (((end - start) + kScatterWaves - 1) / kScatterWaves + 63) / 64 * 64;
     const int q0 = min(start + wv * quarter, end), q1 = min(q0 + quarter, end);
     int* mine = tables + wv * Cc;
+    const gptr<int32_t> cellp = gmem(d.cell);
     __syncthreads();
-    for (int i = q0 + lane; i < q1; i += 64) atomicAdd(&mine[d.cell[i]], 1);
+    for (int i = q0 + lane; i < q1; i += 64) atomicAdd(&mine[cellp[i]], 1);
     __syncthreads();
-    const int* brow = d.counts + (size_t)w.y * Cc;
+    const gptr<int32_t> brow = gmem(d.counts) + (size_t)w.y * Cc;
     for (int c = threadIdx.x; c < Cc; c += blockDim.x) {
         int run = brow[c];
         for (int q = 0; q < kScatterWaves; ++q) {
@@ -320,7 +336,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
         int c = 0;
         R ry = R(0), rvx = R(0), rvy = R(0), rvz = R(0);
         if (valid) {
-            c = d.cell[i];
+            c = cellp[i];
             ry = src.y[i];
             rvx = src.vx[i];
             rvy = src.vy[i];
@@ -412,9 +428,9 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
     if (c < w.z) {
         const P4<double> b = particles<double>(d, (int)(s & 1));
         const int n = d.count[c], o = d.offset[c];
-        double* vx = b.vx + o;
-        double* vy = b.vy + o;
-        double* vz = b.vz + o;
+        const gptr<double> vx = b.vx + o;
+        const gptr<double> vy = b.vy + o;
+        const gptr<double> vz = b.vz + o;
         if (do_collide && n >= 2) {
             double crm = d.crmax[c];
             const double mreal = (((0.5 * (double)n) * (double)(n - 1)) * crm) * d.kntc + d.rem[c];
@@ -468,21 +484,22 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
 }
 
 // ------------------------------------------------------- collide (fast)
-// The same NTC candidates (pair and acceptance drawn per candidate from the
-// cell's counter-based stream) processed in parallel rounds on velocities
-// staged in LDS.  A candidate that shares a particle with a lower-numbered
-// pending candidate waits for a later round (claims by atomicMin in an LDS
-// table), so every executed candidate sees exactly the velocities of some
-// sequential order: NTC in distribution.  The acceptance test of a candidate
-// uses max(crmax at cell start, its own c_r); crmax is raised at the end of
-// the cell.
-//
-// Cells with at least kCoopMin particles are processed by the whole
-// workgroup in rounds of blockDim candidates; smaller cells by one wavefront
-// each in rounds of 64.  The mode depends only on the cell's particle count,
-// so results depend only on the cell's data and stream, not on which
-// workgroup, launch shape or group the cell runs in.
-
+// The fast modes draw the same kind of NTC candidates as the sequential
+// scheme (pair and acceptance uniform per candidate from the cell's
+// counter-based stream) and run them either
+//   - groups of G lanes per cell (k_collide_group, G = 4..32 fixed per
+//     instance) for instances whose collision cells hold fewer than kCoopMin
+//     particles on average, or
+//   - a whole workgroup per cell (k_collide_fast), on velocities staged in
+//     LDS, in parallel rounds of blockDim candidates.  A candidate that shares
+//     a particle with a lower-numbered pending candidate waits for a later
+//     round (claims by atomicMin in an LDS table), so every executed
+//     candidate sees exactly the velocities of some sequential order: NTC in
+//     distribution.  Its acceptance test uses max(crmax at cell start, its
+//     own c_r); crmax is raised at the end of the cell.
+// The choice depends only on the instance's particles per collision cell, so
+// results depend only on the instance's data and streams, not on the group,
+// the launch shape or the workgroup a cell lands in.
 template <class R> struct Cand;
 template <> struct Cand<float> {
     __device__ __forceinline__ static void draw(Stream& st, float& a, float& b, float& c) {
@@ -528,9 +545,9 @@ __device__ __forceinline__ void draw_candidate(const InstDesc& d, uint32_t s, in
 }
 
 // Execute a candidate that owns both of its particles.
-template <class R>
-__device__ __forceinline__ void run_candidate(Pend<R>& p, Stream& st, R crmr, R* vx, R* vy,
-                                              R* vz, int o, R& lane_max, uint32_t& lane_coll) {
+template <class R, class V>
+__device__ __forceinline__ void run_candidate(Pend<R>& p, Stream& st, R crmr, V vx, V vy, V vz,
+                                              int o, R& lane_max, uint32_t& lane_coll) {
     const int i = o + p.i, j = o + p.j;
     const R xi = vx[i], yi = vy[i], zi = vz[i];
     const R xj = vx[j], yj = vy[j], zj = vz[j];
@@ -554,68 +571,6 @@ __device__ __forceinline__ void run_candidate(Pend<R>& p, Stream& st, R crmr, R*
     p.k = -1;
 }
 
-// NTC of one cell by one wavefront (rounds of 64 candidates).
-template <class R>
-__device__ void wave_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, R* vx, R* vy,
-                         R* vz, uint32_t* tab) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long lt = lanes_below(lane);
-    const double crm0 = d.crmax[c];
-    const double mreal = (((0.5 * (double)nc) * (double)(nc - 1)) * crm0) * d.kntc + d.rem[c];
-    const double mf = floor(mreal);
-    const int64_t M = (int64_t)mf;
-    const R crmr = (R)crm0;
-    R lane_max = R(0);
-    uint32_t lane_coll = 0;
-    int64_t next = 0;
-    Pend<R> p;
-    p.k = -1;
-    p.i = p.j = 0;
-    p.acc = R(0);
-    Stream st(d.key0, d.key1, s, (uint32_t)c, 0u, kTagColl);
-    for (;;) {
-        const bool idle = p.k < 0;
-        const unsigned long long im = __ballot(idle);
-        if (idle) {
-            const int64_t k = next + __popcll(im & lt);
-            if (k < M) draw_candidate<R>(d, s, c, nc, k, p, st);
-        }
-        next += __popcll(im);
-        const bool active = p.k >= 0;
-        if (__ballot(active) == 0ull) break;
-        const int hi = p.i & (kClaimTable - 1), hj = p.j & (kClaimTable - 1);
-        if (active) {
-            atomicMin(&tab[hi], (uint32_t)p.k);
-            atomicMin(&tab[hj], (uint32_t)p.k);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const bool win = active && tab[hi] == (uint32_t)p.k && tab[hj] == (uint32_t)p.k;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (active) {
-            tab[hi] = 0xFFFFFFFFu;
-            tab[hj] = 0xFFFFFFFFu;
-        }
-        if (win) run_candidate<R>(p, st, crmr, vx, vy, vz, o, lane_max, lane_coll);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
-    double mx = (double)lane_max;
-    uint32_t cc = lane_coll;
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double other = __shfl_xor(mx, off, 64);
-        mx = other > mx ? other : mx;
-        cc += __shfl_xor(cc, off, 64);
-    }
-    if (lane == 0) {
-        d.rem[c] = mreal - mf;
-        if (mx > crm0) d.crmax[c] = mx;
-        d.ncoll[c] += cc;
-    }
-}
-
 struct CoopShared {
     int idle[kFastWaves];
     double mx[kFastWaves];
@@ -625,9 +580,9 @@ struct CoopShared {
 
 // NTC of one cell by the whole workgroup (rounds of blockDim candidates).
 // Every thread of the workgroup must call it.
-template <class R>
-__device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, R* vx, R* vy,
-                         R* vz, uint32_t* tab, CoopShared& sh) {
+template <class R, class V>
+__device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, V vx, V vy, V vz,
+                         uint32_t* tab, CoopShared& sh) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const unsigned long long lt = lanes_below(lane);
     const double crm0 = d.crmax[c];
@@ -673,7 +628,7 @@ __device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, R*
             tab[hi] = 0xFFFFFFFFu;
             tab[hj] = 0xFFFFFFFFu;
         }
-        if (win) run_candidate<R>(p, st, crmr, vx, vy, vz, o, lane_max, lane_coll);
+        if (win) run_candidate<R, V>(p, st, crmr, vx, vy, vz, o, lane_max, lane_coll);
     }
     double mx = (double)lane_max;
     uint32_t cc = lane_coll;
@@ -705,9 +660,9 @@ __device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, R*
 // Sampling sums of one cell: per lane over a strided share of the cell, then
 // a fixed butterfly over the wavefront (and, in workgroup mode, the wavefront
 // partials added in wavefront order).
-template <class R>
-__device__ __forceinline__ void cell_moments(const R* vx, const R* vy, const R* vz, int o, int nc,
-                                             int first, int stride, double tot[kMoments]) {
+template <class R, class V>
+__device__ __forceinline__ void cell_moments(V vx, V vy, V vz, int o, int nc, int first,
+                                             int stride, double tot[kMoments]) {
     Mom m;
     mom_zero(m);
     for (int q = first; q < nc; q += stride)
@@ -716,51 +671,22 @@ __device__ __forceinline__ void cell_moments(const R* vx, const R* vy, const R* 
     for (int k = 0; k < kMoments; ++k) tot[k] = wave_sum_fixed(m.s[k]);
 }
 
-template <class R>
-__global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc* __restrict__ descs,
-                                                                 const int4* __restrict__ work,
-                                                                 int cap, int do_collide) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ CoopShared sh;
-    const int nw = blockDim.x >> 6;
-    uint32_t* claims = (uint32_t*)smem;
-    R* lds_v = (R*)(claims + kCoopTable);
-    const int4 w = work[blockIdx.x];
-    const InstDesc& d = descs[w.x];
-    const int c0 = w.y, c1 = w.z;
-    const int64_t s = d.sc->step_done;
-    const bool sample = (d.phase_mask & kPhaseSample) && s > d.n_transient;
-    const P4<R> g = particles<R>(d, (int)(s & 1));
-    const int s0 = d.offset[c0];
-    const int n = d.offset[c1 - 1] + d.count[c1 - 1] - s0;
-    const bool staged = n <= cap;
-    R *vx, *vy, *vz;
-    if (staged) {
-        vx = lds_v;
-        vy = lds_v + cap;
-        vz = lds_v + 2 * cap;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            vx[i] = g.vx[s0 + i];
-            vy[i] = g.vy[s0 + i];
-            vz[i] = g.vz[s0 + i];
-        }
-    } else {
-        vx = g.vx + s0;
-        vy = g.vy + s0;
-        vz = g.vz + s0;
-    }
-    for (int i = threadIdx.x; i < kCoopTable; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // cells of at least kCoopMin particles: one at a time, whole workgroup
+// The cells [c0, c1) of a staged block, one at a time with the whole
+// workgroup.  Inlined once for velocities in LDS and once for velocities in
+// global memory, so each copy addresses its memory directly (LDS accesses
+// become ds_* instructions rather than flat ones).
+template <class R, class V>
+__device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int c0, int c1,
+                                              int s0, V vx, V vy, V vz, uint32_t* claims,
+                                              CoopShared& sh, bool do_collide, bool sample) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int c = c0; c < c1; ++c) {
         const int nc = d.count[c];
-        if (nc < kCoopMin) continue;
         const int o = d.offset[c] - s0;
-        if (do_collide) coop_ntc<R>(d, (uint32_t)s, c, nc, o, vx, vy, vz, claims, sh);
+        if (do_collide && nc >= 2) coop_ntc<R, V>(d, s, c, nc, o, vx, vy, vz, claims, sh);
         if (sample) {
             double tot[kMoments];
-            cell_moments<R>(vx, vy, vz, o, nc, (int)threadIdx.x, (int)blockDim.x, tot);
+            cell_moments<R, V>(vx, vy, vz, o, nc, (int)threadIdx.x, (int)blockDim.x, tot);
             if (lane == 0)
                 for (int k = 0; k < kMoments; ++k) sh.mom[wv][k] = tot[k];
             __syncthreads();
@@ -775,32 +701,195 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
             __syncthreads();
         }
     }
-    // smaller cells: one wavefront each
-    uint32_t* tab = claims + wv * kClaimTable;
-    int rank = 0;
-    for (int c = c0; c < c1; ++c) {
-        const int nc = d.count[c];
-        if (nc >= kCoopMin) continue;
-        if ((rank++ % nw) != wv) continue;
-        const int o = d.offset[c] - s0;
-        if (do_collide && nc >= 2) wave_ntc<R>(d, (uint32_t)s, c, nc, o, vx, vy, vz, tab);
-        if (sample) {
-            double tot[kMoments];
-            cell_moments<R>(vx, vy, vz, o, nc, lane, 64, tot);
-            if (lane == 0) {
+}
+
+template <class R>
+__global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc* __restrict__ descs,
+                                                                 const int4* __restrict__ work,
+                                                                 int cap, int do_collide) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ CoopShared sh;
+    uint32_t* claims = (uint32_t*)smem;
+    R* lds_v = (R*)(claims + kCoopTable);
+    const int4 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int c0 = w.y, c1 = w.z;
+    const int64_t s = d.sc->step_done;
+    const bool sample = (d.phase_mask & kPhaseSample) && s > d.n_transient;
+    const P4<R> g = particles<R>(d, (int)(s & 1));
+    const int s0 = d.offset[c0];
+    const int n = d.offset[c1 - 1] + d.count[c1 - 1] - s0;
+    for (int i = threadIdx.x; i < kCoopTable; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
+    if (n <= cap) {
+        R* vx = lds_v;
+        R* vy = lds_v + cap;
+        R* vz = lds_v + 2 * cap;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            vx[i] = g.vx[s0 + i];
+            vy[i] = g.vy[s0 + i];
+            vz[i] = g.vz[s0 + i];
+        }
+        __syncthreads();
+        collide_cells<R, R*>(d, (uint32_t)s, c0, c1, s0, vx, vy, vz, claims, sh, do_collide, sample);
+        __syncthreads();
+        if (do_collide) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                g.vx[s0 + i] = vx[i];
+                g.vy[s0 + i] = vy[i];
+                g.vz[s0 + i] = vz[i];
+            }
+        }
+    } else {
+        // a block fuller than the staging room works on global memory
+        __syncthreads();
+        collide_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, s0, g.vx + s0, g.vy + s0, g.vz + s0,
+                                  claims, sh, do_collide, sample);
+    }
+}
+
+// NTC of small cells by groups of G lanes (G = 4..32, a power of two fixed
+// per instance from its particles per collision cell): each group of a
+// wavefront owns one cell at a time and runs that cell's candidates in rounds
+// of G, with a claim table of its own in LDS, on velocities the workgroup has
+// staged in LDS; the group then reduces the cell's sampling sums.  The groups
+// of a wavefront run in lockstep, so a round needs no barrier.
+template <class R, class V>
+__device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c0, int c1, int s0,
+                                            V vx, V vy, V vz, uint32_t* wtab, int G,
+                                            bool do_collide, bool sample) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int ngw = 64 / G;
+    const int grp = lane / G;
+    const unsigned long long gmask = (G == 64 ? ~0ull : ((1ull << G) - 1ull)) << (grp * G);
+    const unsigned long long lt = lanes_below(lane) & gmask;
+    const int tsize = kGroupTableFactor * G;
+    uint32_t* tab = wtab + grp * tsize;
+    const int stride = nw * ngw;
+    for (int base = c0; base < c1; base += stride) {
+        const int c = base + wv * ngw + grp;
+        const bool has = c < c1;
+        int nc = 0, o = 0;
+        int64_t M = 0;
+        double crm0 = 0.0, mreal = 0.0, mf = 0.0;
+        if (has) {
+            nc = d.count[c];
+            o = d.offset[c] - s0;
+            if (do_collide && nc >= 2) {
+                crm0 = d.crmax[c];
+                mreal = (((0.5 * (double)nc) * (double)(nc - 1)) * crm0) * d.kntc + d.rem[c];
+                mf = floor(mreal);
+                M = (int64_t)mf;
+            }
+        }
+        const R crmr = (R)crm0;
+        R lane_max = R(0);
+        uint32_t lane_coll = 0;
+        int64_t next = 0;
+        Pend<R> p;
+        p.k = -1;
+        p.i = p.j = 0;
+        p.acc = R(0);
+        Stream st(d.key0, d.key1, s, (uint32_t)c, 0u, kTagColl);
+        for (;;) {
+            const bool idle = p.k < 0;
+            const unsigned long long im = __ballot(idle) & gmask;
+            if (idle && has) {
+                const int64_t k = next + __popcll(im & lt);
+                if (k < M) draw_candidate<R>(d, s, c, nc, k, p, st);
+            }
+            next += __popcll(im);
+            const bool active = p.k >= 0;
+            if (__ballot(active) == 0ull) break;
+            const int hi = p.i & (tsize - 1), hj = p.j & (tsize - 1);
+            if (active) {
+                atomicMin(&tab[hi], (uint32_t)p.k);
+                atomicMin(&tab[hj], (uint32_t)p.k);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const bool win = active && tab[hi] == (uint32_t)p.k && tab[hj] == (uint32_t)p.k;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (active) {
+                tab[hi] = 0xFFFFFFFFu;
+                tab[hj] = 0xFFFFFFFFu;
+            }
+            if (win) run_candidate<R, V>(p, st, crmr, vx, vy, vz, o, lane_max, lane_coll);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        // group reductions (butterflies inside the group)
+        double mx = (double)lane_max;
+        uint32_t cc = lane_coll;
+        Mom m;
+        mom_zero(m);
+        if (has && sample)
+            for (int q = lane - grp * G; q < nc; q += G)
+                mom_add(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
+        for (int off = G >> 1; off >= 1; off >>= 1) {
+            const double other = __shfl_xor(mx, off, 64);
+            mx = other > mx ? other : mx;
+            cc += __shfl_xor(cc, off, 64);
+#pragma unroll
+            for (int k = 0; k < kMoments; ++k) m.s[k] += __shfl_xor(m.s[k], off, 64);
+        }
+        if (has && (lane & (G - 1)) == 0) {
+            if (do_collide && nc >= 2) {
+                d.rem[c] = mreal - mf;
+                if (mx > crm0) d.crmax[c] = mx;
+                d.ncoll[c] += cc;
+            }
+            if (sample) {
                 double* a = d.acc + (size_t)c * kMoments;
 #pragma unroll
-                for (int k = 0; k < kMoments; ++k) a[k] += tot[k];
+                for (int k = 0; k < kMoments; ++k) a[k] += m.s[k];
             }
         }
     }
-    __syncthreads();
-    if (staged && do_collide) {
+}
+
+template <class R>
+__global__ __launch_bounds__(64 * kFastWaves) void k_collide_group(const InstDesc* __restrict__ descs,
+                                                                  const int4* __restrict__ work,
+                                                                  int cap, int do_collide) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* claims = (uint32_t*)smem;  // kFastWaves x 64 x kGroupTableFactor entries
+    R* lds_v = (R*)(claims + kFastWaves * 64 * kGroupTableFactor);
+    const int4 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int c0 = w.y, c1 = w.z, G = w.w;
+    const int64_t s = d.sc->step_done;
+    const bool sample = (d.phase_mask & kPhaseSample) && s > d.n_transient;
+    const P4<R> g = particles<R>(d, (int)(s & 1));
+    const int s0 = d.offset[c0];
+    const int n = d.offset[c1 - 1] + d.count[c1 - 1] - s0;
+    for (int i = threadIdx.x; i < kFastWaves * 64 * kGroupTableFactor; i += blockDim.x)
+        claims[i] = 0xFFFFFFFFu;
+    uint32_t* wtab = claims + (threadIdx.x >> 6) * 64 * kGroupTableFactor;
+    if (n <= cap) {
+        R* vx = lds_v;
+        R* vy = lds_v + cap;
+        R* vz = lds_v + 2 * cap;
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            g.vx[s0 + i] = vx[i];
-            g.vy[s0 + i] = vy[i];
-            g.vz[s0 + i] = vz[i];
+            vx[i] = g.vx[s0 + i];
+            vy[i] = g.vy[s0 + i];
+            vz[i] = g.vz[s0 + i];
         }
+        __syncthreads();
+        group_cells<R, R*>(d, (uint32_t)s, c0, c1, s0, vx, vy, vz, wtab, G, do_collide, sample);
+        __syncthreads();
+        if (do_collide) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                g.vx[s0 + i] = vx[i];
+                g.vy[s0 + i] = vy[i];
+                g.vz[s0 + i] = vz[i];
+            }
+        }
+    } else {
+        // a block fuller than the staging room works on global memory
+        __syncthreads();
+        group_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, s0, g.vx + s0, g.vy + s0, g.vz + s0, wtab,
+                                G, do_collide, sample);
     }
 }
 
@@ -911,18 +1000,28 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
     if (phase & (kPhaseCollide | kPhaseSample)) {
         const int do_collide = (phase & kPhaseCollide) ? 1 : 0;
         if (mode == kFp64Det) {
-            hipLaunchKernelGGL(k_collide_det, dim3(w.n_cblocks), dim3(64), 0, st, w.desc, w.cblocks,
+            hipLaunchKernelGGL(k_collide_det, dim3(w.n_gblocks), dim3(64), 0, st, w.desc, w.gblocks,
                                do_collide);
         } else {
-            hipLaunchKernelGGL((k_collide_fast<R>), dim3(w.n_cblocks), dim3(64 * kFastWaves),
-                               fast_collide_lds_bytes(mode, w.fast_cap), st, w.desc, w.cblocks,
-                               w.fast_cap, do_collide);
+            if (w.n_cblocks)
+                hipLaunchKernelGGL((k_collide_fast<R>), dim3(w.n_cblocks), dim3(64 * kFastWaves),
+                                   fast_collide_lds_bytes(mode, w.fast_cap), st, w.desc, w.cblocks,
+                                   w.fast_cap, do_collide);
+            if (w.n_gblocks)
+                hipLaunchKernelGGL((k_collide_group<R>), dim3(w.n_gblocks), dim3(64 * kFastWaves),
+                                   group_collide_lds_bytes(mode, w.group_cap), st, w.desc, w.gblocks,
+                                   w.group_cap, do_collide);
         }
     }
     mark(6);
 }
 
 }  // namespace
+
+size_t group_collide_lds_bytes(Mode mode, int cap) {
+    const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
+    return (size_t)kFastWaves * 64 * kGroupTableFactor * sizeof(uint32_t) + 3 * (size_t)cap * rb;
+}
 
 size_t fast_collide_lds_bytes(Mode mode, int cap) {
     const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
@@ -954,6 +1053,8 @@ hipError_t configure_kernels(size_t max_dynamic_lds) {
     };
     set((const void*)k_collide_fast<float>);
     set((const void*)k_collide_fast<double>);
+    set((const void*)k_collide_group<float>);
+    set((const void*)k_collide_group<double>);
     set((const void*)k_move_hist<float, true>);
     set((const void*)k_move_hist<float, false>);
     set((const void*)k_move_hist<double, true>);

@@ -229,14 +229,55 @@ void drop_graph(dsmc_group* g) {
 }
 
 int auto_cpb(const dsmc_handle* h, int target_particles) {
-    // Cells of kCoopMin or more particles get a workgroup each; smaller ones
-    // are packed about target_particles (and at least one cell per wavefront)
-    // to a workgroup.
+    // Cells per workgroup of the staged collide: one by default; a tuning
+    // target packs cells up to that many particles.
     const double per_cell = (double)h->plan.N / (double)h->plan.Cc;
-    if (per_cell >= kCoopMin) return 1;
-    const double target = target_particles > 0 ? (double)target_particles : 2048.0;
-    const int c = (int)std::floor(target / std::max(per_cell, 1.0));
-    return std::max(kFastWaves, std::min(c, 256));
+    if (target_particles <= 0) return 1;
+    const int c = (int)std::floor((double)target_particles / std::max(per_cell, 1.0));
+    return std::max(1, std::min(c, 64));
+}
+
+// Lanes per cell of the small-cell collide: about one per eight particles,
+// a power of two from 4 to 32.
+int group_width(double per_cell) {
+    int G = 4;
+    while (G < 32 && G * 16 <= per_cell) G *= 2;
+    return G;
+}
+
+// Order a work list for the XCDs: workgroups are dealt to the 8 XCDs in
+// turn (workgroup p runs on XCD p mod 8), so the list, taken in its natural
+// instance-major order, is cut into 8 contiguous stripes and stripe x is
+// dealt to positions x, x+8, ...  All tiles of a small instance, and
+// neighbouring tiles of a large one, then share one XCD's L2, where the
+// scatter's partial cache lines to the same cell regions merge.
+template <class T>
+std::vector<T> xcd_stripes(const std::vector<T>& in) {
+    constexpr int kX = 8;
+    const size_t n = in.size();
+    if (n <= (size_t)kX) return in;
+    std::vector<size_t> beg(kX + 1);
+    for (int x = 0; x <= kX; ++x) beg[x] = n * (size_t)x / kX;
+    std::vector<size_t> next(beg.begin(), beg.end() - 1);
+    std::vector<T> out;
+    out.reserve(n);
+    for (size_t p = 0; out.size() < n; ++p) {
+        int x = (int)(p % kX);
+        if (next[x] >= beg[x + 1]) {
+            // this stripe is used up (the stripes differ by at most one):
+            // take from the stripe with the most left
+            int best = -1;
+            size_t left = 0;
+            for (int y = 0; y < kX; ++y)
+                if (beg[y + 1] - next[y] > left) {
+                    left = beg[y + 1] - next[y];
+                    best = y;
+                }
+            x = best;
+        }
+        out.push_back(in[next[x]++]);
+    }
+    return out;
 }
 
 // (Re)build the device work lists and launch shapes of a group.
@@ -245,9 +286,9 @@ int rebuild(dsmc_group* g) {
     const int n = (int)g->members.size();
     std::vector<InstDesc> descs(n);
     std::vector<int2> tiles;
-    std::vector<int4> cols, cblocks;
+    std::vector<int4> cols, cblocks, gblocks;
     int max_cc = 1;
-    int cap = 64;
+    int cap = 64, group_cap = 64;
     for (int i = 0; i < n; ++i) {
         dsmc_handle* h = g->members[i];
         InstDesc d = h->desc;
@@ -265,35 +306,49 @@ int rebuild(dsmc_group* g) {
         for (int ch = 0; ch < (d.Cc + kColThreads - 1) / kColThreads; ++ch)
             for (int sgi = 0; sgi < d.nseg; ++sgi) cols.push_back(make_int4(i, ch, sgi, 0));
         max_cc = std::max(max_cc, d.Cc);
+        const double per_cell = (double)d.N / (double)d.Cc;
         if (g->mode == kFp64Det) {
-            for (int c = 0; c < d.Cc; c += 64) cblocks.push_back(make_int4(i, c, std::min(c + 64, d.Cc), 0));
+            // one lane per cell, 64 cells per wavefront
+            for (int c = 0; c < d.Cc; c += 64) gblocks.push_back(make_int4(i, c, std::min(c + 64, d.Cc), 64));
+        } else if (per_cell < kCoopMin) {
+            // groups of G lanes per cell, one cell per group per pass
+            const int G = group_width(per_cell);
+            const int cpb = (kFastWaves * 64 / G) * (g->ppb > 0 ? std::max(1, g->ppb / 2048) : 1);
+            for (int c = 0; c < d.Cc; c += cpb) gblocks.push_back(make_int4(i, c, std::min(c + cpb, d.Cc), G));
+            const double per_block = per_cell * cpb;
+            group_cap = std::max(group_cap, (int)std::ceil(per_block + 4.0 * std::sqrt(per_block) + 32.0));
         } else {
             const int cpb = auto_cpb(h, g->ppb);
             for (int c = 0; c < d.Cc; c += cpb) cblocks.push_back(make_int4(i, c, std::min(c + cpb, d.Cc), 0));
-            // staging room for a block's particles: mean + 6 Poisson sigma
+            // staging room for a block's particles: mean + 4 Poisson sigma
             // (a fuller block works on global memory instead)
-            const double per_block = (double)d.N / (double)d.Cc * cpb;
-            const int want = (int)std::ceil(per_block + 6.0 * std::sqrt(per_block) + 64.0);
+            const double per_block = per_cell * cpb;
+            const int want = (int)std::ceil(per_block + 4.0 * std::sqrt(per_block) + 32.0);
             cap = std::max(cap, want);
         }
     }
+    tiles = xcd_stripes(tiles);
+    cblocks = xcd_stripes(cblocks);
+    gblocks = xcd_stripes(gblocks);
     // fit the fast-collide staging area into the device's LDS
     const size_t rb = g->mode == kFp32Fast ? 4 : 8;
     const int max_lds = device_max_lds();
     const size_t fixed = (size_t)kCoopTable * 4 + 1024;  // claim table + static shared
     const int cap_max = (int)(((size_t)max_lds - fixed) / (3 * rb));
     cap = std::min(cap, cap_max);
+    const size_t gfixed = (size_t)kFastWaves * 64 * kGroupTableFactor * 4;
+    group_cap = std::min(group_cap, (int)(((size_t)max_lds - gfixed) / (3 * rb)));
     if ((size_t)max_cc * 4 * kScatterWaves > (size_t)max_lds)
         return fail(&g->err, DSMC_ERR_INVALID_ARG, "collision cells exceed the LDS tables of the scatter");
 
-    const size_t need = align_up(sizeof(InstDesc) * std::max(n, 1)) + align_up(sizeof(int2) * std::max<size_t>(tiles.size(), 1)) +
-                        align_up(sizeof(int4) * std::max<size_t>(cols.size(), 1)) +
-                        align_up(sizeof(int4) * std::max<size_t>(cblocks.size(), 1));
+    auto bytes_of = [](size_t k, size_t sz) { return align_up(sz * std::max<size_t>(k, 1)); };
+    const size_t need = bytes_of(n, sizeof(InstDesc)) + bytes_of(tiles.size(), sizeof(int2)) +
+                        bytes_of(cols.size(), sizeof(int4)) + bytes_of(cblocks.size(), sizeof(int4)) +
+                        bytes_of(gblocks.size(), sizeof(int4));
+    // the stream may still be using the previous lists
+    HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
     if (need > g->d_bytes) {
-        if (g->d_mem) {
-            (void)hipStreamSynchronize(g->stream);
-            (void)hipFree(g->d_mem);
-        }
+        if (g->d_mem) (void)hipFree(g->d_mem);
         g->d_mem = nullptr;
         g->d_bytes = 0;
         HIP_TRY(&g->err, hipMalloc(&g->d_mem, need));
@@ -302,18 +357,19 @@ int rebuild(dsmc_group* g) {
     char* base = (char*)g->d_mem;
     size_t o = 0;
     InstDesc* d_desc = (InstDesc*)(base + o);
-    o += align_up(sizeof(InstDesc) * std::max(n, 1));
+    o += bytes_of(n, sizeof(InstDesc));
     int2* d_tiles = (int2*)(base + o);
-    o += align_up(sizeof(int2) * std::max<size_t>(tiles.size(), 1));
+    o += bytes_of(tiles.size(), sizeof(int2));
     int4* d_cols = (int4*)(base + o);
-    o += align_up(sizeof(int4) * std::max<size_t>(cols.size(), 1));
+    o += bytes_of(cols.size(), sizeof(int4));
     int4* d_cb = (int4*)(base + o);
-    // the stream may still be using the previous lists
-    HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
+    o += bytes_of(cblocks.size(), sizeof(int4));
+    int4* d_lb = (int4*)(base + o);
     if (n) HIP_TRY(&g->err, hipMemcpy(d_desc, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
     if (!tiles.empty()) HIP_TRY(&g->err, hipMemcpy(d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice));
     if (!cols.empty()) HIP_TRY(&g->err, hipMemcpy(d_cols, cols.data(), sizeof(int4) * cols.size(), hipMemcpyHostToDevice));
     if (!cblocks.empty()) HIP_TRY(&g->err, hipMemcpy(d_cb, cblocks.data(), sizeof(int4) * cblocks.size(), hipMemcpyHostToDevice));
+    if (!gblocks.empty()) HIP_TRY(&g->err, hipMemcpy(d_lb, gblocks.data(), sizeof(int4) * gblocks.size(), hipMemcpyHostToDevice));
     g->work.desc = d_desc;
     g->work.n_inst = n;
     g->work.tiles = d_tiles;
@@ -322,6 +378,9 @@ int rebuild(dsmc_group* g) {
     g->work.n_cols = (int)cols.size();
     g->work.cblocks = d_cb;
     g->work.n_cblocks = (int)cblocks.size();
+    g->work.gblocks = d_lb;
+    g->work.n_gblocks = (int)gblocks.size();
+    g->work.group_cap = group_cap;
     g->work.max_cc = max_cc;
     g->work.fast_cap = cap;
     g->phase = (g->solo && n == 1 && g->members[0]->p.debug_phase_mask)
@@ -882,10 +941,10 @@ int dsmc_group_autotune(dsmc_group* g, int32_t* tile_mult_out, int32_t* ppb_out)
     if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
     if (g->members.empty()) return fail(&g->err, DSMC_ERR_STATE, "group has no members");
     const std::string sig = group_signature(g);
-    int best_tm = 1, best_ppb = 2048;
+    int best_tm = 1, best_ppb = 0;
     if (!tune_lookup(sig, &best_tm, &best_ppb)) {
         static const int tms[] = {1, 2, 4};
-        static const int ppbs[] = {1024, 2048, 4096};
+        static const int ppbs[] = {0, 2048, 4096};
         hipEvent_t e0, e1;
         HIP_TRY(&g->err, hipEventCreate(&e0));
         HIP_TRY(&g->err, hipEventCreate(&e1));
