@@ -217,9 +217,11 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
     return v;
 }
 
-// Per instance: count[c] = column total, offset = exclusive scan of counts in
-// cell order, segment bases = offset + exclusive scan over segments.  Also
-// advances the instance's step counter (and the sampled-step count).
+// Per instance: for each cell, the segment sums become their exclusive
+// prefix over segments and count[c] the column total; offset = exclusive
+// scan of counts in cell order.  Also advances the instance's step counter
+// (and the sampled-step count).  The segment loads of a cell are independent,
+// so they are issued together.
 __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restrict__ descs,
                                                      int do_scan) {
     const InstDesc& d = descs[blockIdx.x];
@@ -227,15 +229,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (do_scan) {
         const int Cc = d.Cc, nseg = d.nseg;
+        const gptr<int32_t> seg = gmem(d.segsum);
         const int per = (Cc + kScanThreads - 1) / kScanThreads;
         const int c0 = min(tid * per, Cc), c1 = min(c0 + per, Cc);
         int local = 0;
         for (int c = c0; c < c1; ++c) {
+            // column sums of the segments -> exclusive prefix over segments
             int tot = 0;
-            for (int g = 0; g < nseg; ++g) {
-                int* e = d.segsum + (size_t)g * Cc + c;
-                const int v = *e;
-                *e = tot;
+            int g = 0;
+            for (; g + 8 <= nseg; g += 8) {
+                int v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = seg[(size_t)(g + u) * Cc + c];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    seg[(size_t)(g + u) * Cc + c] = tot;
+                    tot += v[u];
+                }
+            }
+            for (; g < nseg; ++g) {
+                const int v = seg[(size_t)g * Cc + c];
+                seg[(size_t)g * Cc + c] = tot;
                 tot += v;
             }
             d.count[c] = tot;
@@ -253,9 +267,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
         int run = incl - local + (wv ? wsum[wv - 1] : 0);
         for (int c = c0; c < c1; ++c) {
             d.offset[c] = run;
-            const int base = run;
             run += d.count[c];
-            for (int g = 0; g < nseg; ++g) d.segsum[(size_t)g * Cc + c] += base;
         }
         if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != d.N) atomicOr(&d.sc->status, 2);
     }
@@ -267,14 +279,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
     }
 }
 
+// Per-tile scatter bases of a segment: offset[c] + the prefix of the earlier
+// segments + the counts of the earlier tiles of this segment.
 __global__ __launch_bounds__(kColThreads) void k_colprefix(const InstDesc* __restrict__ descs,
                                                          const int4* __restrict__ work) {
     const int4 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
     const int c = w.y * kColThreads + (int)threadIdx.x;
     if (c >= d.Cc) return;
+    int run = d.offset[c] + gmem(d.segsum)[(size_t)w.z * d.Cc + c];
     const int t0 = w.z * kSegTiles, t1 = min(t0 + kSegTiles, d.tiles);
-    int run = d.segsum[(size_t)w.z * d.Cc + c];
     const gptr<int32_t> cnt = gmem(d.counts);
     for (int t = t0; t < t1; ++t) {
         const gptr<int32_t> e = cnt + (size_t)t * d.Cc + c;
@@ -297,20 +311,32 @@ __global__ __launch_bounds__(kColThreads) void k_colprefix(const InstDesc* __res
 // round needs no barrier.  The destination of every slot is base + (number
 // of earlier slots of the tile with the same cell): exactly a stable
 // counting sort.
+//
+// Tiles of at most stage_max slots are first laid out in LDS in destination
+// order (the tile's cells in order, each cell's slots in slot order) and then
+// written out by consecutive threads, so each cell's run from the tile
+// leaves as one contiguous write instead of one partial cache line per slot;
+// this matters at high Kn, where the slots of a tile spread over many cells.
 template <class R>
 __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __restrict__ descs,
-                                                             const int2* __restrict__ work) {
-    extern __shared__ int tables[];  // kScatterWaves x Cc
+                                                             const int2* __restrict__ work,
+                                                             int stage_max) {
+    extern __shared__ int tables[];  // kScatterWaves x Cc, then Cc, then the staging area
     const int2 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
     const int Cc = d.Cc;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int k = threadIdx.x; k < kScatterWaves * Cc; k += blockDim.x) tables[k] = 0;
     const int64_t s = d.sc->step_done;
     const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
     const P4<R> dst = particles<R>(d, (int)(s & 1));
     const int start = w.y * d.tile_items;
     const int end = min(start + d.tile_items, d.N);
+    const bool staged = d.tile_items <= stage_max;
+    int* delta = tables + kScatterWaves * Cc;           // tile base minus local base, per cell
+    int* stage_pos = delta + Cc;                         // staged: destination of each local slot
+    // staged: 4 x stage_max record words, 16-byte aligned
+    R* stage_rec = (R*)(tables + (((kScatterWaves + 1) * Cc + stage_max + 3) & ~3));
+    for (int k = threadIdx.x; k < kScatterWaves * Cc; k += blockDim.x) tables[k] = 0;
     const int quarter = (((end - start) + kScatterWaves - 1) / kScatterWaves + 63) / 64 * 64;
     const int q0 = min(start + wv * quarter, end), q1 = min(q0 + quarter, end);
     int* mine = tables + wv * Cc;
@@ -319,12 +345,41 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
     for (int i = q0 + lane; i < q1; i += 64) atomicAdd(&mine[cellp[i]], 1);
     __syncthreads();
     const gptr<int32_t> brow = gmem(d.counts) + (size_t)w.y * Cc;
+    // per-wavefront bases; when staged, the tile's count of each cell goes
+    // to delta[] (which exists only then)
     for (int c = threadIdx.x; c < Cc; c += blockDim.x) {
-        int run = brow[c];
+        const int b = brow[c];
+        int run = b;
         for (int q = 0; q < kScatterWaves; ++q) {
             const int v = tables[q * Cc + c];
             tables[q * Cc + c] = run;
             run += v;
+        }
+        if (staged) delta[c] = run - b;
+    }
+    if (staged) {
+        // exclusive scan of the tile's cell counts over cells: the local base
+        // of each cell; delta = tile base - local base
+        __shared__ int wsum[kParticleThreads / 64];
+        __syncthreads();
+        const int per = (Cc + (int)blockDim.x - 1) / (int)blockDim.x;
+        const int a0 = min((int)threadIdx.x * per, Cc), a1 = min(a0 + per, Cc);
+        int local = 0;
+        for (int c = a0; c < a1; ++c) local += delta[c];
+        int incl = local;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += u;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        int run = incl - local;
+        for (int q = 0; q < wv; ++q) run += wsum[q];
+        for (int c = a0; c < a1; ++c) {
+            const int cnt = delta[c];
+            delta[c] = brow[c] - run;
+            run += cnt;
         }
     }
     __syncthreads();
@@ -354,13 +409,33 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
             // (lowest lane) advances it: same wavefront, program order
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             if ((m & lt) == 0ull) mine[c] = pos + __popcll(m);
-            dst.y[pos] = ry;
-            dst.vx[pos] = rvx;
-            dst.vy[pos] = rvy;
-            dst.vz[pos] = rvz;
+            if (staged) {
+                const int l = pos - delta[c];
+                stage_pos[l] = pos;
+                stage_rec[l] = ry;
+                stage_rec[stage_max + l] = rvx;
+                stage_rec[2 * stage_max + l] = rvy;
+                stage_rec[3 * stage_max + l] = rvz;
+            } else {
+                dst.y[pos] = ry;
+                dst.vx[pos] = rvx;
+                dst.vy[pos] = rvy;
+                dst.vz[pos] = rvz;
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
+    }
+    if (staged) {
+        __syncthreads();
+        const int n = end - start;
+        for (int l = threadIdx.x; l < n; l += blockDim.x) {
+            const int pos = stage_pos[l];
+            dst.y[pos] = stage_rec[l];
+            dst.vx[pos] = stage_rec[stage_max + l];
+            dst.vy[pos] = stage_rec[2 * stage_max + l];
+            dst.vz[pos] = stage_rec[3 * stage_max + l];
+        }
     }
 }
 
@@ -987,7 +1062,8 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
         hipLaunchKernelGGL(k_colprefix, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
         mark(4);
         hipLaunchKernelGGL((k_scatter<R>), dim3(w.n_tiles), dim3(kParticleThreads),
-                           hist_lds * kScatterWaves, st, w.desc, w.tiles);
+                           scatter_lds_bytes(mode, w.max_cc, w.stage_max), st, w.desc, w.tiles,
+                           w.stage_max);
     } else {
         mark(2);
         hipLaunchKernelGGL(k_scan, dim3(w.n_inst), dim3(kScanThreads), 0, st, w.desc, 0);
@@ -1017,6 +1093,13 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
 }
 
 }  // namespace
+
+size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max) {
+    const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
+    if (stage_max <= 0) return (size_t)kScatterWaves * max_cc * sizeof(int);
+    return (size_t)(kScatterWaves + 1) * max_cc * sizeof(int) +
+           (size_t)stage_max * (sizeof(int) + 4 * rb) + 16;
+}
 
 size_t group_collide_lds_bytes(Mode mode, int cap) {
     const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);

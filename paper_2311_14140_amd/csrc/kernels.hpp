@@ -21,6 +21,7 @@ struct Work {
     int n_gblocks;
     int group_cap;          // particles a small-cell collide workgroup stages in LDS
     int max_cc;             // largest collision-cell count (LDS of histograms)
+    int stage_max;          // tiles of at most this many slots are staged in LDS by the scatter
     int fast_cap;           // particles a fast-collide workgroup stages in LDS
 };
 
@@ -35,6 +36,7 @@ void launch_finalize(const InstDesc* d_desc, int n_inst, hipStream_t s);
 void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s);
 size_t fast_collide_lds_bytes(Mode mode, int cap);
 size_t group_collide_lds_bytes(Mode mode, int cap);
+size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max);
 // Allow dynamic LDS up to max_dynamic_lds bytes for the kernels that use it.
 hipError_t configure_kernels(size_t max_dynamic_lds);
 

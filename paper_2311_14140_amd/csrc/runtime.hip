@@ -57,11 +57,23 @@ struct Plan {
         off_rem, off_acc, off_ncoll, off_est, off_sc, off_desc, total;
 };
 
-int base_items_per_thread(int32_t N, int32_t Cc) {
+// Slots of a particle tile the scatter can lay out in LDS before writing.
+int stage_slots(size_t rb) { return rb == 4 ? 2048 : 1024; }
+
+int base_items_per_thread(int32_t N, int32_t Cc, size_t rb) {
     // Tiles of 256 * k slots with at least 4 slots per collision cell keep
-    // the per-tile histogram traffic near one byte per particle.
+    // the per-tile histogram traffic near one byte per particle.  A small
+    // instance is cut into at least ~128 tiles, so the workgroups an XCD has
+    // in flight belong to one or two instances whose scatter destinations
+    // fit in its L2, where the partial cache lines of a random scatter merge
+    // before they reach HBM.
     int k = (int)std::ceil(4.0 * (double)Cc / (double)kParticleThreads);
     k = std::max(1, std::min(64, k));
+    const int k_small = (int)std::ceil((double)N / (128.0 * kParticleThreads));
+    if (k_small < k) {
+        // and such tiles are small enough for the scatter to stage in LDS
+        k = std::max(1, std::min(k_small, stage_slots(rb) / kParticleThreads));
+    }
     const int64_t need = (int64_t)((N + kParticleThreads - 1) / kParticleThreads);
     if (need < k) k = (int)std::max<int64_t>(1, need);
     return k;
@@ -112,7 +124,7 @@ Plan make_plan(const dsmc_params* p) {
     q.crmax0 = 5.0 * std::sqrt(2.0 * p->wall_temperature);
     q.sqrt_tw = std::sqrt(p->wall_temperature);
     q.inv_dy = (double)q.Cc / q.H;
-    const int k = base_items_per_thread(q.N, q.Cc);
+    const int k = base_items_per_thread(q.N, q.Cc, q.rb);
     q.tile_items = k * kParticleThreads;
     q.tiles = (q.N + q.tile_items - 1) / q.tile_items;
     q.nseg = (q.tiles + kSegTiles - 1) / kSegTiles;
@@ -340,6 +352,12 @@ int rebuild(dsmc_group* g) {
     group_cap = std::min(group_cap, (int)(((size_t)max_lds - gfixed) / (3 * rb)));
     if ((size_t)max_cc * 4 * kScatterWaves > (size_t)max_lds)
         return fail(&g->err, DSMC_ERR_INVALID_ARG, "collision cells exceed the LDS tables of the scatter");
+    // staged scatter for members whose tiles fit, if the LDS can hold it
+    int stage_max = stage_slots(rb);
+    bool any_staged = false;
+    for (const InstDesc& d : descs) any_staged |= d.tile_items <= stage_max;
+    if (!any_staged || scatter_lds_bytes((Mode)g->mode, max_cc, stage_max) > (size_t)max_lds)
+        stage_max = 0;
 
     auto bytes_of = [](size_t k, size_t sz) { return align_up(sz * std::max<size_t>(k, 1)); };
     const size_t need = bytes_of(n, sizeof(InstDesc)) + bytes_of(tiles.size(), sizeof(int2)) +
@@ -382,6 +400,7 @@ int rebuild(dsmc_group* g) {
     g->work.n_gblocks = (int)gblocks.size();
     g->work.group_cap = group_cap;
     g->work.max_cc = max_cc;
+    g->work.stage_max = stage_max;
     g->work.fast_cap = cap;
     g->phase = (g->solo && n == 1 && g->members[0]->p.debug_phase_mask)
                    ? g->members[0]->p.debug_phase_mask
