@@ -4,20 +4,25 @@
 A step is one pass of the whole hot path (move with body force and diffuse
 walls, stable counting sort by collision cell, NTC collisions, FP64 moment
 sampling) over every particle of the workload.  The default workload is the
-single-instance FP32-velocity / FP64-accumulator channel at Kn = 0.1 with 300
-cells x 1000 particles per cell (3e5 particles), inputs resident in HBM.  The
-timed steps are sampling steps (the warm-up steps are the transient).
+batched mix: 256 independent force-driven channel instances (Kn log-uniform
+in [0.05, 10], force uniform in [0.001, 0.02], 50..2000 cells, 20..200
+particles per cell; 2.6e7 particles in all) in FP32 velocities with FP64
+moment accumulators, stepped as one group with graph-replayed steps and
+inputs resident in HBM.  The timed steps are sampling steps (the warm-up
+steps are the transient).
 
 Prints one JSON line: particle-steps/s, the roofline of the dominant kernel
 (its algorithmic bytes over its average duration from HIP events on the
-library's stream), the plain FP64 deterministic path on the same workload, and
-the CPU oracle timed on this host for a bounded sample.
+library's stream), the plain FP64 path (each instance alone, sequential
+per-cell NTC) on the same instances, the served request stream (p50/p99 time
+from arrival to moments on the host, FP32 batched against plain FP64), the
+single-instance workloads, and the CPU oracle timed on this host for a
+bounded sample.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -28,6 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = ("particle-steps/s at fixed moment accuracy (FP32 batched vs FP64 plain); "
           "p50/p99 solve latency")
+MIX_DESC = ("256 instances: Kn log-uniform [0.05, 10], F uniform [0.001, 0.02], "
+            "cells uniform [50, 2000], particles/cell uniform [20, 200]")
 
 
 def kernel_bytes(phase: str, N: int, Cc: int, rb: int, coll_frac: float, sampling: bool) -> float:
@@ -48,7 +55,8 @@ def kernel_bytes(phase: str, N: int, Cc: int, rb: int, coll_frac: float, samplin
     return 0.0
 
 
-PROFILE_TAGS = {"cfg1": "kernels_cfg1_kn0.1_300x1000_fp32"}
+PROFILE_TAGS = {"cfg1": "kernels_cfg1_kn0.1_300x1000_fp32",
+                "cfg3": "kernels_cfg3_batched256_fp32"}
 
 
 def kernel_source_hash() -> str:
@@ -64,30 +72,48 @@ def measured_traffic(workload: str, kernel: str):
     """Copy-calibrated HBM bytes per launch of a kernel from the committed
     rocprofv3 counter summary, or None when there is none or the kernels have
     changed since the counters were taken."""
-    import json as _json
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     tag = PROFILE_TAGS.get(workload)
     if not tag or not os.path.exists(path):
         return None
     with open(path) as fh:
-        rec = _json.load(fh).get(tag)
+        rec = json.load(fh).get(tag)
     if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec["bytes_per_launch"].get(kernel)
 
 
-def cpu_oracle_rate(params, seconds: float):
-    import oracle
-    o = oracle.Oracle(params)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        o.step(2)
-        steps += 2
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return o.N * steps / el, steps, el
+class Subject:
+    """The timed workload: one instance, or the batched mix as one group."""
+
+    def __init__(self, dsmc, params_list):
+        self.sols = [dsmc.Solver(p) for p in params_list]
+        self.group = None
+        if len(self.sols) > 1:
+            self.group = dsmc.Group()
+            for s in self.sols:
+                self.group.add(s)
+        self.N = sum(s.N for s in self.sols)
+        self.Cc = sum(s.Cc for s in self.sols)
+
+    def step(self, n):
+        (self.group or self.sols[0]).step(n)
+
+    def sync(self):
+        (self.group or self.sols[0]).sync()
+
+    def profile(self, n):
+        # profiling a member of a group profiles the group's steps
+        return self.sols[0].profile(n)
+
+    def sample(self):
+        return [s.sample(reset=True) for s in self.sols]
+
+    def close(self):
+        if self.group:
+            self.group.close()
+        for s in self.sols:
+            s.close()
 
 
 def _timed(torch, step, sync, n):
@@ -100,7 +126,7 @@ def _timed(torch, step, sync, n):
     return time.perf_counter() - t
 
 
-def time_single(dsmc, torch, p, steps):
+def time_single(dsmc, torch, p, steps, label):
     """particle-steps/s of one instance (sampling steps, graph-replayed)."""
     p = p.with_(n_transient=4)
     with dsmc.Solver(p) as s:
@@ -109,49 +135,80 @@ def time_single(dsmc, torch, p, steps):
         prof = s.profile(4)
         return {"value": s.N * steps / el, "unit": "particle-steps/s", "particles": s.N,
                 "steps": steps, "ms_per_step": 1e3 * el / steps,
-                "workload": f"Kn={p.kn}, F={p.body_force}, {p.n_cells} cells x "
+                "workload": f"{label}: Kn={p.kn}, F={p.body_force}, {p.n_cells} cells x "
                             f"{p.particles_per_cell}/cell, n_sub={p.n_sub}, FP32",
                 "kernel_ms_per_step": {k: prof[k] / 4 for k in dsmc.Solver.PHASES}}
 
 
-def time_batched(dsmc, torch, steps):
-    """particle-steps/s of the 256-instance mix stepped as one group."""
+def fp64_plain(dsmc, torch, params_list, steps):
+    """The plain FP64 path: each instance alone, deterministic mode
+    (sequential per-cell NTC, bit-identical to the oracle)."""
+    from synth import FP64_DETERMINISTIC
+    ps_total, el_total = 0, 0.0
+    for p in params_list:
+        with dsmc.Solver(p.with_(n_transient=0, precision=FP64_DETERMINISTIC)) as d:
+            d.step(2)
+            el_total += _timed(torch, d.step, d.sync, steps)
+            ps_total += d.N * steps
+    return {"value": ps_total / el_total, "unit": "particle-steps/s", "steps": steps,
+            "instances": len(params_list), "dtype": "f64",
+            "note": "each instance alone, sequential-per-cell NTC, bit-identical to the oracle"}
+
+
+def serve(n_requests, rate_hz, precision, batched, budget):
+    """Serve the first n requests of the Poisson trace; returns the summary."""
     import synth
-    ps = synth.config3_instances(256)
-    g = dsmc.Group()
-    sols = []
-    for p in ps:
-        s = dsmc.Solver(p.with_(n_transient=4))
-        g.add(s)
-        sols.append(s)
-    N = sum(s.N for s in sols)
-    g.step(8)
-    el = _timed(torch, g.step, g.sync, steps)
-    prof = sols[0].profile(4)
-    out = {"value": N * steps / el, "unit": "particle-steps/s", "particles": N,
-           "instances": len(sols), "steps": steps, "ms_per_step": 1e3 * el / steps,
-           "workload": "256 instances: Kn log-uniform [0.05, 10], F uniform [0.001, 0.02], "
-                       "cells uniform [50, 2000], particles/cell uniform [20, 200], FP32",
-           "kernel_ms_per_step": {k: prof[k] / 4 for k in dsmc.Solver.PHASES}}
-    g.close()
-    for s in sols:
-        s.close()
-    return out
+    from paper_2311_14140_amd.serve import GpuExecutor, PlainGpuExecutor, Request, Server
+    trace = synth.serving_trace(n_requests, rate_hz=rate_hz, precision=precision)
+    reqs = [Request(i, t, p, steps) for i, (t, p, steps) in enumerate(trace)]
+    if batched:
+        ex = GpuExecutor()
+        srv = Server(ex, budget_bytes=budget, max_slots=256, quantum=100)
+    else:
+        ex = PlainGpuExecutor()
+        srv = Server(ex, budget_bytes=budget, max_slots=1, quantum=1000)
+    _, summ = srv.run(reqs)
+    if batched:
+        ex.close()
+    summ["rate_hz"] = rate_hz
+    summ["mode"] = "FP32 batched (one group, up to 256 running)" if batched else \
+        "FP64 plain (one solve at a time)"
+    return summ
+
+
+def cpu_oracle_rate(params_list, seconds: float):
+    """The oracle stepping the given instances in turn, 2 steps at a time,
+    for about ``seconds`` of stepping (set-up not timed)."""
+    import oracle
+    from synth import FP64_DETERMINISTIC
+    orc = [oracle.Oracle(p.with_(precision=FP64_DETERMINISTIC)) for p in params_list]
+    ps, el = 0, 0.0
+    while el < seconds:
+        for o in orc:
+            t = time.perf_counter()
+            o.step(2)
+            el += time.perf_counter() - t
+            ps += 2 * o.N
+            if el >= seconds:
+                break
+    return ps / el, ps, el
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="cfg1", choices=["cfg0", "cfg1", "cfg2"])
-    ap.add_argument("--profile-steps", type=int, default=100)
+    ap.add_argument("--workload", default="cfg3", choices=["cfg0", "cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--fp64-steps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the large-instance and batched-mix measurements")
-    ap.add_argument("--extra-steps", type=int, default=20)
+                    help="skip the single-instance workloads and the served stream")
+    ap.add_argument("--extra-steps", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the Poisson trace to serve in each mode (2000 = full)")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of the plain device copy run after the timed region, whose "
                          "HBM counters calibrate the kernels' (0 = skip)")
@@ -165,69 +222,88 @@ def main():
 
     import torch
     from paper_2311_14140_amd import dsmc
-    from synth import WORKLOADS, FP64_DETERMINISTIC
+    import synth
+    from synth import WORKLOADS
+
+    def log(msg):
+        print("# " + msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
-    base, _ = WORKLOADS[args.workload]
-    p = base.with_(n_transient=args.warmup)
-    rb = 4 if p.precision == dsmc.DSMC_FP32_FAST else 8
-    s = dsmc.Solver(p)
-    N, Cc = s.N, s.Cc
-    print(f"# workload {args.workload}: N={N} cells={p.n_cells} n_sub={p.n_sub} "
-          f"precision={p.precision} warmup={args.warmup} steps={args.steps}",
-          file=sys.stderr, flush=True)
-    s.step(args.warmup)
-    s.sync()
-    s.sample(reset=True)
+    if args.workload == "cfg3":
+        plist = [p.with_(n_transient=args.warmup) for p in synth.config3_instances(256)]
+        wdesc = f"cfg3: {MIX_DESC}, FP32 velocities + FP64 accumulators, one group"
+    else:
+        base, _ = WORKLOADS[args.workload]
+        plist = [base.with_(n_transient=args.warmup)]
+        wdesc = (f"{args.workload}: Kn={base.kn}, F={base.body_force}, {base.n_cells} cells x "
+                 f"{base.particles_per_cell} particles/cell, n_sub={base.n_sub}")
+    rb = 4 if plist[0].precision == dsmc.DSMC_FP32_FAST else 8
+    sub = Subject(dsmc, plist)
+    N, Cc = sub.N, sub.Cc
+    log(f"workload {args.workload}: {len(plist)} instance(s), N={N}, collision cells={Cc}, "
+        f"warmup={args.warmup} steps={args.steps}")
+    sub.step(args.warmup)
+    sub.sync()
+    sub.sample()
 
     # ---- timed region: K steps, graph-replayed, inputs resident in HBM
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.step(args.steps)
-    s.sync()
+    sub.step(args.steps)
+    sub.sync()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    el = t1 - t0
+    el = time.perf_counter() - t0
     rate = N * args.steps / el
-    est = s.sample(reset=True)
-    coll_frac = 2.0 * est["n_collisions"] / (N * args.steps)
-    print(f"# timed {args.steps} steps in {el:.4f} s: {rate:.4e} particle-steps/s; "
-          f"mass flow {est['mass_flow']:.6f}", file=sys.stderr, flush=True)
+    est = sub.sample()
+    n_coll = sum(e["n_collisions"] for e in est)
+    coll_frac = 2.0 * n_coll / (N * args.steps)
+    log(f"timed {args.steps} steps in {el:.4f} s: {rate:.4e} particle-steps/s")
 
     # ---- per-kernel durations: HIP events around every kernel on the
     # library's stream, over separately launched steps of the same run
-    prof = s.profile(args.profile_steps)
+    prof = sub.profile(args.profile_steps)
     kern = {k: prof[k] / args.profile_steps for k in dsmc.Solver.PHASES}
     dom = max(kern, key=kern.get)
     dom_bytes = kernel_bytes(dom, N, Cc, rb, coll_frac, True)
     achieved = dom_bytes / (kern[dom] * 1e-3) / 1e9
     step_bytes = sum(kernel_bytes(k, N, Cc, rb, coll_frac, True) for k in kern)
-    print("# per-kernel ms/step: " + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()),
-          file=sys.stderr, flush=True)
-    s.close()
+    log("per-kernel ms/step: " + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()))
+    sub.close()
 
-    # ---- the plain FP64 deterministic path on the same workload
+    # ---- the plain FP64 path on the same instances (a sample of the mix)
     fp64 = None
     if args.fp64_steps > 0:
-        q = base.with_(n_transient=0, precision=FP64_DETERMINISTIC)
-        with dsmc.Solver(q) as d:
-            d.step(2)
-            d.sync()
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            d.step(args.fp64_steps)
-            d.sync()
-            b = time.perf_counter()
-        fp64 = {"value": N * args.fp64_steps / (b - a), "unit": "particle-steps/s",
-                "steps": args.fp64_steps, "dtype": "f64",
-                "note": "sequential-per-cell NTC, bit-identical to the oracle"}
+        sample = plist[::16]
+        fp64 = fp64_plain(dsmc, torch, sample, args.fp64_steps)
+        fp64["sample"] = f"{len(sample)} instances (every 16th), {args.fp64_steps} steps each" \
+            if len(plist) > 1 else "the same instance"
+        log(f"fp64 plain: {fp64['value']:.4e} particle-steps/s")
 
-    # ---- other workloads of the same hot path, timed the same way
-    extra = {}
+    # ---- other workloads of the same hot path, and the served stream
+    extra, serving = {}, None
     if not args.no_extra:
-        extra["cfg2_large_instance"] = time_single(dsmc, torch, WORKLOADS["cfg2"][0].with_(
-            n_sub=2), args.extra_steps)
-        extra["cfg3_batched_256"] = time_batched(dsmc, torch, args.extra_steps)
+        extra["cfg1_single_instance"] = time_single(dsmc, torch, WORKLOADS["cfg1"][0],
+                                                    args.extra_steps, "cfg1")
+        log(f"cfg1: {extra['cfg1_single_instance']['value']:.4e}")
+        extra["cfg2_large_instance"] = time_single(dsmc, torch, WORKLOADS["cfg2"][0].with_(n_sub=2),
+                                                   max(2, args.extra_steps // 10), "cfg2")
+        log(f"cfg2: {extra['cfg2_large_instance']['value']:.4e}")
+        if args.serve_requests > 0:
+            free, _ = torch.cuda.mem_get_info()
+            budget = int(0.8 * free)
+            fp32 = serve(args.serve_requests, 200.0, synth.FP32_FAST, True, budget)
+            log(f"served FP32 batched: p50 {fp32['p50_s']:.3f} s, p99 {fp32['p99_s']:.3f} s")
+            plain = serve(args.serve_requests, 200.0, synth.FP64_DETERMINISTIC, False, budget)
+            log(f"served FP64 plain: p50 {plain['p50_s']:.3f} s, p99 {plain['p99_s']:.3f} s")
+            per_req = fp32["particle_steps"] / max(1, fp32["served"])
+            cap = rate / per_req   # requests/s the batched path sustains
+            low = serve(args.serve_requests, 0.7 * cap, synth.FP32_FAST, True, budget)
+            log(f"served FP32 at 0.7 capacity ({0.7 * cap:.1f}/s): p50 {low['p50_s']:.3f} s")
+            serving = {"trace": f"first {args.serve_requests} requests of the Poisson trace "
+                                f"(mean 200/s, parameters from the batched-mix distribution, "
+                                f"transient per Kn + 5000 sampling steps each)",
+                       "budget_bytes": budget, "fp32_batched": fp32, "fp64_plain": plain,
+                       "fp32_batched_0.7_capacity": low}
 
     # a plain copy of known size (outside the timed region): what the
     # FETCH_SIZE / WRITE_SIZE counters read for it calibrates the kernels'
@@ -242,11 +318,13 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cq = base.with_(precision=FP64_DETERMINISTIC)
-        r, st, sec = cpu_oracle_rate(cq, args.cpu_seconds)
+        sample = plist[::16]
+        r, ps, sec = cpu_oracle_rate(sample, args.cpu_seconds)
         cpu = {"value": r, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"{st} steps of the same {N}-particle instance from its initial "
-                         f"state, FP64, one thread, {sec:.1f} s"}
+               "sample": f"{ps} particle-steps: {len(sample)} instance(s) of the workload "
+                         f"stepped in turn from their initial state, FP64, one thread, "
+                         f"{sec:.1f} s of stepping"}
+        log(f"cpu oracle: {r:.4e} particle-steps/s")
 
     line = {
         "metric": METRIC,
@@ -261,10 +339,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if rb == 4 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: Kn={p.kn}, F={p.body_force}, "
-                               f"{p.n_cells} cells x {p.particles_per_cell} particles/cell, "
-                               f"n_sub={p.n_sub}, FP32 velocities + FP64 accumulators"
-                   if rb == 4 else f"{args.workload}", "particles": N,
+        "config": {"workload": wdesc, "instances": len(plist), "particles": N,
                    "collision_cells": Cc, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -275,8 +350,9 @@ def main():
                           "frac": step_bytes / (el / args.steps) / 1e9 / HBM_PEAK_GBS},
         "kernel_ms_per_step": kern,
         "fp64_plain": fp64,
+        "speedup_vs_fp64_plain": rate / fp64["value"] if fp64 else None,
+        "serving": serving,
         "cpu_baseline": cpu,
-        "mass_flow": est["mass_flow"],
         "other_workloads": extra,
     }
     print(json.dumps(line), flush=True)

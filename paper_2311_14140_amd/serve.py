@@ -16,7 +16,8 @@ Each instance's arithmetic and ordering do not depend on the group it runs
 in, so a request's result is the same (bit for bit) alone and in the mix.
 
 The scheduling logic is independent of the device: ``Server`` drives any
-``Executor``; ``GpuExecutor`` runs the instances on the GPU through the C ABI.
+``Executor``; ``GpuExecutor`` runs the instances on the GPU through the C ABI
+as one group, ``PlainGpuExecutor`` steps each instance on its own.
 """
 from __future__ import annotations
 
@@ -105,6 +106,37 @@ class GpuExecutor(Executor):
 
     def close(self):
         self._group.close()
+
+
+class PlainGpuExecutor(Executor):
+    """Every instance stepped on its own (no group): with ``max_slots=1`` this
+    is the plain one-solve-at-a-time service the batched one is compared with."""
+
+    def __init__(self, stream=None):
+        from . import dsmc
+        self._d = dsmc
+        self._stream = stream
+        self._running = []
+
+    def footprint(self, params) -> int:
+        return self._d.footprint_bytes(params)
+
+    def start(self, params):
+        s = self._d.Solver(params, stream=self._stream, arena="torch")
+        self._running.append(s)
+        return s
+
+    def step(self, n: int) -> None:
+        for s in self._running:
+            s.step(n)
+        for s in self._running:
+            s.sync()
+
+    def finish(self, handle) -> dict:
+        self._running.remove(handle)
+        out = handle.sample()
+        handle.close()
+        return out
 
 
 class Server:

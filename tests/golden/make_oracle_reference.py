@@ -10,6 +10,15 @@ mass flow rate.  Replicas are independent, so the across-replica spread
 gives the standard error of the mean profiles.
 
     python tests/golden/make_oracle_reference.py --workload cfg1 --replicas 64
+
+For the batched mix (``--workload cfg3``) every one of its instances is run
+with ``--replicas`` replicas (seed of instance i, replica r:
+synth.seed_of(3, i, r)) on a short common schedule (MIX_TRANSIENT steps, then
+MIX_SAMPLING sampling steps).  Both sides of a comparison run the same
+schedule, so the expected profiles agree whether or not the flow is steady.
+To keep the file small each profile is stored as MIX_BINS averages over
+equal runs of cells (bin j of an instance with C cells holds the plain mean
+over cells floor(j C / B) .. floor((j + 1) C / B) - 1).
 """
 from __future__ import annotations
 
@@ -31,6 +40,8 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 QUANTITIES = ("n", "ux", "T", "pxy", "qx")
+MIX_TRANSIENT, MIX_SAMPLING, MIX_BINS = 100, 300, 16
+
 SCHEDULES = {
     # workload: (params, workload index for seeds, transient, sampling steps)
     "cfg0": (synth.CONFIG0, 0, 1000, 1000),
@@ -46,13 +57,53 @@ def run_replica(params, transient, sampling):
     return {q: e[q].copy() for q in QUANTITIES}, e["mass_flow"]
 
 
+def bin_means(profile, bins=MIX_BINS):
+    c = len(profile)
+    edges = [(j * c) // bins for j in range(bins + 1)]
+    return np.array([np.mean(profile[edges[j]:edges[j + 1]]) for j in range(bins)])
+
+
+def run_mix_replica(params):
+    prof, q = run_replica(params, MIX_TRANSIENT, MIX_SAMPLING)
+    return {name: bin_means(prof[name]) for name in QUANTITIES}, q
+
+
+def main_mix(args):
+    inst = synth.config3_instances()
+    jobs = [(i, r, inst[i].with_(seed=synth.seed_of(3, i, r), precision=0))
+            for i in range(len(inst)) for r in range(args.replicas)]
+    # longest first keeps the pool busy to the end
+    jobs.sort(key=lambda j: -j[2].n_particles)
+    t0 = time.time()
+    out = {q: np.zeros((len(inst), args.replicas, MIX_BINS)) for q in QUANTITIES}
+    Q = np.zeros((len(inst), args.replicas))
+    with ThreadPoolExecutor(args.workers) as ex:
+        for n, ((i, r, _), (prof, q)) in enumerate(
+                zip(jobs, ex.map(lambda j: run_mix_replica(j[2]), jobs))):
+            for name in QUANTITIES:
+                out[name][i, r] = prof[name]
+            Q[i, r] = q
+            if n % 64 == 63 or n == len(jobs) - 1:
+                print(f"{n + 1}/{len(jobs)} runs ({time.time() - t0:.0f} s)", flush=True)
+    src = open(oracle.SRC, "rb").read()
+    meta = dict(workload="cfg3", instances=len(inst), transient=MIX_TRANSIENT,
+                sampling_steps=MIX_SAMPLING, bins=MIX_BINS, replicas=args.replicas,
+                seed_rule="synth.seed_of(3, i, r)", mix="synth.config3_instances()",
+                oracle_sha256=hashlib.sha256(src).hexdigest())
+    path = os.path.join(HERE, f"oracle_cfg3_mix_r0_{args.replicas}.npz")
+    np.savez_compressed(path, mass_flow=Q, **out, meta=json.dumps(meta))
+    print("wrote", path, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=sorted(SCHEDULES), required=True)
+    ap.add_argument("--workload", choices=sorted(SCHEDULES) + ["cfg3"], required=True)
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--workers", type=int, default=max(1, (os.cpu_count() or 2) - 2))
     ap.add_argument("--first", type=int, default=0, help="index of the first replica")
     args = ap.parse_args()
+    if args.workload == "cfg3":
+        return main_mix(args)
     base, k, transient, sampling = SCHEDULES[args.workload]
     reps = [base.with_(seed=synth.seed_of(k, 0, r))
             for r in range(args.first, args.first + args.replicas)]
