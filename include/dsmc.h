@@ -198,14 +198,17 @@ int dsmc_group_destroy(dsmc_group *g);
 
 /* Launch-shape tuning of a group: tile_mult multiplies each member's base
  * particle tile (the slots one move or scatter workgroup walks; 1..16) and
- * particles_per_block packs that many particles' worth of collision cells
- * into one workgroup of the LDS-staged collide (instances with 256 or more
- * particles per collision cell; the workgroup takes its cells one after
- * another); 0 keeps the automatic choice (1, one cell per workgroup).
- * Results do not depend on either. */
+ * particles_per_block sets how many particles' worth of collision cells one
+ * collide workgroup takes.  For instances with fewer than 256 particles per
+ * collision cell in the fast modes this is the size of a sort bucket (a
+ * power of two of cells, default about 2048 particles in FP32 and 1024 in
+ * FP64): the global sort orders particles by bucket and the collide
+ * workgroup of the bucket sorts it by cell in LDS.  For fuller cells it packs
+ * cells into one LDS-staged collide workgroup (default one cell each).
+ * 0 keeps the automatic choice.  Results do not depend on either. */
 int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t particles_per_block);
 /* Time every pair of tile_mult in {1, 2, 4} and particles_per_block in
- * {0, 2048, 4096} on the group's own steps (4 steps each; they are real
+ * {0, 1024, 4096} on the group's own steps (4 steps each; they are real
  * steps of the members) and keep the fastest.  The choice is cached per group
  * shape (precision and the particles and collision cells of every member), in
  * the process and, if DSMC_AUTOTUNE_CACHE names a file, across processes.

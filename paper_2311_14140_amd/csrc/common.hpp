@@ -17,6 +17,7 @@ constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
 constexpr int kCoopMin = 256;          // cells this full are collided by a whole workgroup
 constexpr int kGroupTableFactor = 16;  // claim-table entries per lane of a small-cell group
 constexpr int kCoopTable = kFastWaves * kClaimTable;  // its claim table (the wave tables together)
+constexpr int kMaxCellsPerKey = 256;   // cells of one sort bucket (a power of two up to this)
 
 // Scalars an instance keeps on the device so that a step is the same launch
 // sequence every time (and can be replayed from a graph).
@@ -36,6 +37,14 @@ struct DevScalars {
 // structure-of-arrays: buf[b][0..3] = y, vx, vy, vz of buffer b.  After step
 // s the state lives in buffer (s & 1): the move of step s works in place on
 // buffer ((s - 1) & 1) and the stable scatter writes buffer (s & 1).
+//
+// The global sort is by key = cell >> key_shift.  With key_shift = 0 the key
+// is the collision cell and the scatter leaves the state sorted by cell
+// (kcount / koffset are count / offset).  With key_shift > 0 a key is a
+// bucket of 2^key_shift consecutive cells: the scatter leaves each bucket's
+// particles contiguous, in their previous order, and the collide kernel
+// finishes the sort by cell inside each bucket (writing count / offset).
+// Both orders end as the stable sort of the particles by cell.
 struct InstDesc {
     int32_t N, C, Cc, n_sub;           // particles, sampling cells, collision cells, Cc / C
     int32_t tiles, tile_items, nseg, ppc;  // particle tiles, items per tile, scan segments
@@ -44,10 +53,13 @@ struct InstDesc {
     uint32_t key0, key1;
     uint32_t phase_mask;
     int32_t pad1_;
+    int32_t nkeys, key_shift;          // sort keys, log2 of cells per key
     void* buf[2][4];
-    int32_t* cell;     // N: collision cell of each slot (pre-sort order)
-    int32_t* counts;   // tiles * Cc: per-tile histogram, then per-tile scatter bases
-    int32_t* segsum;   // nseg * Cc: per-segment column sums, then segment bases
+    int32_t* cell;     // N: sort key of each slot (pre-sort order)
+    int32_t* counts;   // tiles * nkeys: per-tile histogram, then per-tile scatter bases
+    int32_t* segsum;   // nseg * nkeys: per-segment column sums, then segment bases
+    int32_t* kcount;   // nkeys: particles per key
+    int32_t* koffset;  // nkeys: first slot of each key
     int32_t* count;    // Cc
     int32_t* offset;   // Cc
     double* crmax;     // Cc

@@ -153,8 +153,8 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* 
     __shared__ int blk_bad;
     const int2 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
-    const int Cc = d.Cc;
-    for (int c = threadIdx.x; c < Cc; c += blockDim.x) hist[c] = 0;
+    const int nk = d.nkeys;
+    for (int c = threadIdx.x; c < nk; c += blockDim.x) hist[c] = 0;
     if (threadIdx.x == 0) blk_bad = 0;
     __syncthreads();
     const int64_t s = d.sc->step_done + 1;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* 
                 b.vz[p] = vz;
             }
             bad |= !(isfinite(vx) && isfinite(vy) && isfinite(vz));
-            c = cell_of<R>(d, y);
+            c = cell_of<R>(d, y) >> d.key_shift;
             cellp[p] = c;
         } else {
             c = cellp[p];
@@ -184,28 +184,29 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* 
     }
     if (kMove && bad) atomicOr(&blk_bad, 1);
     __syncthreads();
-    const gptr<int32_t> row = gmem(d.counts) + (size_t)w.y * Cc;
-    for (int c = threadIdx.x; c < Cc; c += blockDim.x) row[c] = hist[c];
+    const gptr<int32_t> row = gmem(d.counts) + (size_t)w.y * nk;
+    for (int c = threadIdx.x; c < nk; c += blockDim.x) row[c] = hist[c];
     // error path only: a non-finite velocity was seen in this tile
     if (kMove && threadIdx.x == 0 && blk_bad) atomicOr(&d.sc->status, 1);
 }
 
 // ------------------------------------------------------- column scans
-// The tile histograms form a (tiles x Cc) matrix stored tile-major.  The
-// scatter base of (tile t, cell c) is offset[c] + sum_{t' < t} count[t'][c];
+// The tile histograms form a (tiles x nkeys) matrix stored tile-major.  The
+// scatter base of (tile t, key c) is koffset[c] + sum_{t' < t} count[t'][c];
 // it is built column-wise in segments of kSegTiles tiles so that every access
-// is coalesced across consecutive cells.
+// is coalesced across consecutive keys.
 __global__ __launch_bounds__(kColThreads) void k_colsum(const InstDesc* __restrict__ descs,
                                                       const int4* __restrict__ work) {
     const int4 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
     const int c = w.y * kColThreads + (int)threadIdx.x;
-    if (c >= d.Cc) return;
+    const int nk = d.nkeys;
+    if (c >= nk) return;
     const int t0 = w.z * kSegTiles, t1 = min(t0 + kSegTiles, d.tiles);
     const gptr<int32_t> cnt = gmem(d.counts);
     int sum = 0;
-    for (int t = t0; t < t1; ++t) sum += cnt[(size_t)t * d.Cc + c];
-    d.segsum[(size_t)w.z * d.Cc + c] = sum;
+    for (int t = t0; t < t1; ++t) sum += cnt[(size_t)t * nk + c];
+    d.segsum[(size_t)w.z * nk + c] = sum;
 }
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
@@ -217,9 +218,9 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
     return v;
 }
 
-// Per instance: for each cell, the segment sums become their exclusive
-// prefix over segments and count[c] the column total; offset = exclusive
-// scan of counts in cell order.  Also advances the instance's step counter
+// Per instance: for each sort key, the segment sums become their exclusive
+// prefix over segments and kcount[c] the column total; koffset = exclusive
+// scan of kcount in key order.  Also advances the instance's step counter
 // (and the sampled-step count).  The segment loads of a cell are independent,
 // so they are issued together.
 __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restrict__ descs,
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
     __shared__ int wsum[kScanThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (do_scan) {
-        const int Cc = d.Cc, nseg = d.nseg;
+        const int Cc = d.nkeys, nseg = d.nseg;
         const gptr<int32_t> seg = gmem(d.segsum);
         const int per = (Cc + kScanThreads - 1) / kScanThreads;
         const int c0 = min(tid * per, Cc), c1 = min(c0 + per, Cc);
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
                 seg[(size_t)g * Cc + c] = tot;
                 tot += v;
             }
-            d.count[c] = tot;
+            d.kcount[c] = tot;
             local += tot;
         }
         const int incl = wave_incl_scan(local, lane);
@@ -266,8 +267,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
         __syncthreads();
         int run = incl - local + (wv ? wsum[wv - 1] : 0);
         for (int c = c0; c < c1; ++c) {
-            d.offset[c] = run;
-            run += d.count[c];
+            d.koffset[c] = run;
+            run += d.kcount[c];
         }
         if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != d.N) atomicOr(&d.sc->status, 2);
     }
@@ -279,19 +280,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
     }
 }
 
-// Per-tile scatter bases of a segment: offset[c] + the prefix of the earlier
+// Per-tile scatter bases of a segment: koffset[c] + the prefix of the earlier
 // segments + the counts of the earlier tiles of this segment.
 __global__ __launch_bounds__(kColThreads) void k_colprefix(const InstDesc* __restrict__ descs,
                                                          const int4* __restrict__ work) {
     const int4 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
     const int c = w.y * kColThreads + (int)threadIdx.x;
-    if (c >= d.Cc) return;
-    int run = d.offset[c] + gmem(d.segsum)[(size_t)w.z * d.Cc + c];
+    const int nk = d.nkeys;
+    if (c >= nk) return;
+    int run = d.koffset[c] + gmem(d.segsum)[(size_t)w.z * nk + c];
     const int t0 = w.z * kSegTiles, t1 = min(t0 + kSegTiles, d.tiles);
     const gptr<int32_t> cnt = gmem(d.counts);
     for (int t = t0; t < t1; ++t) {
-        const gptr<int32_t> e = cnt + (size_t)t * d.Cc + c;
+        const gptr<int32_t> e = cnt + (size_t)t * nk + c;
         const int v = *e;
         *e = run;
         run += v;
@@ -310,7 +312,8 @@ __global__ __launch_bounds__(kColThreads) void k_colprefix(const InstDesc* __res
 // with its cell, and only the owning wavefront advances its table, so a
 // round needs no barrier.  The destination of every slot is base + (number
 // of earlier slots of the tile with the same cell): exactly a stable
-// counting sort.
+// counting sort.  "Cell" here means the instance's sort key: the collision
+// cell, or a bucket of cells whose sort the collide kernel finishes.
 //
 // Tiles of at most stage_max slots are first laid out in LDS in destination
 // order (the tile's cells in order, each cell's slots in slot order) and then
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
     extern __shared__ int tables[];  // kScatterWaves x Cc, then Cc, then the staging area
     const int2 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
-    const int Cc = d.Cc;
+    const int Cc = d.nkeys;  // the sort keys play the part of cells here
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t s = d.sc->step_done;
     const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
@@ -822,16 +825,17 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
     }
 }
 
-// NTC of small cells by groups of G lanes (G = 4..32, a power of two fixed
-// per instance from its particles per collision cell): each group of a
-// wavefront owns one cell at a time and runs that cell's candidates in rounds
-// of G, with a claim table of its own in LDS, on velocities the workgroup has
-// staged in LDS; the group then reduces the cell's sampling sums.  The groups
-// of a wavefront run in lockstep, so a round needs no barrier.
+// NTC of small cells by groups of G lanes (G = 4..64, a power of two fixed
+// per instance and launch shape): each group of a wavefront owns one cell at
+// a time and runs that cell's candidates in rounds of G, with a claim table
+// of its own in LDS; the group then reduces the cell's sampling sums.  The
+// groups of a wavefront run in lockstep, so a round needs no barrier.  Cell
+// c of [c0, c1) holds lcnt[c - c0] particles from index loff[c - c0] of the
+// velocity arrays.
 template <class R, class V>
-__device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c0, int c1, int s0,
-                                            V vx, V vy, V vz, uint32_t* wtab, int G,
-                                            bool do_collide, bool sample) {
+__device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c0, int c1,
+                                            const int* lcnt, const int* loff, V vx, V vy, V vz,
+                                            uint32_t* wtab, int G, bool do_collide, bool sample) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int ngw = 64 / G;
     const int grp = lane / G;
@@ -847,8 +851,8 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
         int64_t M = 0;
         double crm0 = 0.0, mreal = 0.0, mf = 0.0;
         if (has) {
-            nc = d.count[c];
-            o = d.offset[c] - s0;
+            nc = lcnt[c - c0];
+            o = loff[c - c0];
             if (do_collide && nc >= 2) {
                 crm0 = d.crmax[c];
                 mreal = (((0.5 * (double)nc) * (double)(nc - 1)) * crm0) * d.kntc + d.rem[c];
@@ -923,48 +927,140 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
     }
 }
 
+// Sort of one bucket of cells [c0, c1) by cell, stable: the bucket's n
+// particles sit at slots s0 .. s0 + n - 1 of g in their previous order, and
+// are written to sy, sx, sv, sz (indices 0 .. n - 1) sorted by cell.  Four
+// wavefronts each own a contiguous quarter: a first pass counts each
+// quarter's cells in the wavefront's table wt (kMaxCellsPerKey entries per
+// wavefront); lcnt / loff receive the bucket's per-cell counts and local
+// offsets; the second pass ranks equal cells of a round of 64 slots with
+// bit-sliced ballots, as the global scatter does.  Every thread must call it.
+template <class R, class V>
+__device__ __forceinline__ void bucket_sort(const InstDesc& d, const P4<R>& g, int s0, int n,
+                                            int c0, int ncell, int* wt, int* lcnt, int* loff,
+                                            V sy, V sx, V sv, V sz) {
+    __shared__ int wsum[kFastWaves];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int quarter = ((n + kFastWaves - 1) / kFastWaves + 63) / 64 * 64;
+    const int q0 = min(wv * quarter, n), q1 = min(q0 + quarter, n);
+    int* mine = wt + wv * kMaxCellsPerKey;
+    for (int i = q0 + lane; i < q1; i += 64) atomicAdd(&mine[cell_of<R>(d, g.y[s0 + i]) - c0], 1);
+    __syncthreads();
+    // one thread per cell of the bucket (ncell <= kMaxCellsPerKey <= blockDim)
+    const int c = threadIdx.x;
+    int tot = 0;
+    if (c < ncell)
+        for (int q = 0; q < kFastWaves; ++q) tot += wt[q * kMaxCellsPerKey + c];
+    const int incl = wave_incl_scan(tot, lane);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int run = incl - tot;
+    for (int q = 0; q < wv; ++q) run += wsum[q];
+    if (c < ncell) {
+        lcnt[c] = tot;
+        loff[c] = run;
+        for (int q = 0; q < kFastWaves; ++q) {
+            const int v = wt[q * kMaxCellsPerKey + c];
+            wt[q * kMaxCellsPerKey + c] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const unsigned long long lt = lanes_below(lane);
+    const int nbits = ncell > 1 ? 32 - __builtin_clz((unsigned)(ncell - 1)) : 0;
+    for (int base = q0; base < q1; base += 64) {
+        const int i = base + lane;
+        const bool valid = i < q1;
+        int lc = 0;
+        R ry = R(0), rx = R(0), rv = R(0), rz = R(0);
+        if (valid) {
+            ry = g.y[s0 + i];
+            rx = g.vx[s0 + i];
+            rv = g.vy[s0 + i];
+            rz = g.vz[s0 + i];
+            lc = cell_of<R>(d, ry) - c0;
+        }
+        unsigned long long m = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (lc >> b) & 1;
+            const unsigned long long bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
+        if (valid) {
+            const int pos = mine[lc] + __popcll(m & lt);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if ((m & lt) == 0ull) mine[lc] = pos + __popcll(m);
+            sy[pos] = ry;
+            sx[pos] = rx;
+            sv[pos] = rv;
+            sz[pos] = rz;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+}
+
+// Collide kernel of bucket-sorted instances: one workgroup per bucket (work
+// item: instance, bucket, G).  The bucket is sorted by cell into LDS (or,
+// when fuller than the staging room, into the same slots of the other
+// particle buffer, which is free during this phase), its cells are collided
+// and sampled there, and the sorted records are written back to the bucket's
+// slots together with each cell's count and offset.
 template <class R>
-__global__ __launch_bounds__(64 * kFastWaves) void k_collide_group(const InstDesc* __restrict__ descs,
-                                                                  const int4* __restrict__ work,
-                                                                  int cap, int do_collide) {
+__global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDesc* __restrict__ descs,
+                                                                   const int4* __restrict__ work,
+                                                                   int cap, int do_collide) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* claims = (uint32_t*)smem;  // kFastWaves x 64 x kGroupTableFactor entries
-    R* lds_v = (R*)(claims + kFastWaves * 64 * kGroupTableFactor);
+    int* wt = (int*)(claims + kFastWaves * 64 * kGroupTableFactor);
+    int* lcnt = wt + kFastWaves * kMaxCellsPerKey;
+    int* loff = lcnt + kMaxCellsPerKey;
+    R* lds = (R*)(loff + kMaxCellsPerKey);
     const int4 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
-    const int c0 = w.y, c1 = w.z, G = w.w;
+    const int b = w.y, G = w.z;
+    const int c0 = b << d.key_shift, c1 = min(c0 + (1 << d.key_shift), d.Cc);
     const int64_t s = d.sc->step_done;
     const bool sample = (d.phase_mask & kPhaseSample) && s > d.n_transient;
     const P4<R> g = particles<R>(d, (int)(s & 1));
-    const int s0 = d.offset[c0];
-    const int n = d.offset[c1 - 1] + d.count[c1 - 1] - s0;
+    const int s0 = d.koffset[b], n = d.kcount[b];
     for (int i = threadIdx.x; i < kFastWaves * 64 * kGroupTableFactor; i += blockDim.x)
         claims[i] = 0xFFFFFFFFu;
+    for (int i = threadIdx.x; i < kFastWaves * kMaxCellsPerKey; i += blockDim.x) wt[i] = 0;
+    __syncthreads();
     uint32_t* wtab = claims + (threadIdx.x >> 6) * 64 * kGroupTableFactor;
     if (n <= cap) {
-        R* vx = lds_v;
-        R* vy = lds_v + cap;
-        R* vz = lds_v + 2 * cap;
+        R* sy = lds;
+        R* sx = lds + cap;
+        R* sv = lds + 2 * cap;
+        R* sz = lds + 3 * cap;
+        bucket_sort<R, R*>(d, g, s0, n, c0, c1 - c0, wt, lcnt, loff, sy, sx, sv, sz);
+        group_cells<R, R*>(d, (uint32_t)s, c0, c1, lcnt, loff, sx, sv, sz, wtab, G, do_collide, sample);
+        __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            vx[i] = g.vx[s0 + i];
-            vy[i] = g.vy[s0 + i];
-            vz[i] = g.vz[s0 + i];
-        }
-        __syncthreads();
-        group_cells<R, R*>(d, (uint32_t)s, c0, c1, s0, vx, vy, vz, wtab, G, do_collide, sample);
-        __syncthreads();
-        if (do_collide) {
-            for (int i = threadIdx.x; i < n; i += blockDim.x) {
-                g.vx[s0 + i] = vx[i];
-                g.vy[s0 + i] = vy[i];
-                g.vz[s0 + i] = vz[i];
-            }
+            g.y[s0 + i] = sy[i];
+            g.vx[s0 + i] = sx[i];
+            g.vy[s0 + i] = sv[i];
+            g.vz[s0 + i] = sz[i];
         }
     } else {
-        // a block fuller than the staging room works on global memory
+        const P4<R> o = particles<R>(d, (int)((s - 1) & 1));
+        const gptr<R> sy = o.y + s0, sx = o.vx + s0, sv = o.vy + s0, sz = o.vz + s0;
+        bucket_sort<R, gptr<R>>(d, g, s0, n, c0, c1 - c0, wt, lcnt, loff, sy, sx, sv, sz);
+        group_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, lcnt, loff, sx, sv, sz, wtab, G, do_collide,
+                                sample);
         __syncthreads();
-        group_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, s0, g.vx + s0, g.vy + s0, g.vz + s0, wtab,
-                                G, do_collide, sample);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            g.y[s0 + i] = sy[i];
+            g.vx[s0 + i] = sx[i];
+            g.vy[s0 + i] = sv[i];
+            g.vz[s0 + i] = sz[i];
+        }
+    }
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
+        d.count[c] = lcnt[c - c0];
+        d.offset[c] = s0 + loff[c - c0];
     }
 }
 
@@ -1084,9 +1180,9 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
                                    fast_collide_lds_bytes(mode, w.fast_cap), st, w.desc, w.cblocks,
                                    w.fast_cap, do_collide);
             if (w.n_gblocks)
-                hipLaunchKernelGGL((k_collide_group<R>), dim3(w.n_gblocks), dim3(64 * kFastWaves),
-                                   group_collide_lds_bytes(mode, w.group_cap), st, w.desc, w.gblocks,
-                                   w.group_cap, do_collide);
+                hipLaunchKernelGGL((k_collide_bucket<R>), dim3(w.n_gblocks), dim3(64 * kFastWaves),
+                                   bucket_collide_lds_bytes(mode, w.group_cap), st, w.desc,
+                                   w.gblocks, w.group_cap, do_collide);
         }
     }
     mark(6);
@@ -1101,9 +1197,10 @@ size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max) {
            (size_t)stage_max * (sizeof(int) + 4 * rb) + 16;
 }
 
-size_t group_collide_lds_bytes(Mode mode, int cap) {
+size_t bucket_collide_lds_bytes(Mode mode, int cap) {
     const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
-    return (size_t)kFastWaves * 64 * kGroupTableFactor * sizeof(uint32_t) + 3 * (size_t)cap * rb;
+    return (size_t)kFastWaves * 64 * kGroupTableFactor * sizeof(uint32_t) +
+           (size_t)(kFastWaves + 2) * kMaxCellsPerKey * sizeof(int) + 4 * (size_t)cap * rb;
 }
 
 size_t fast_collide_lds_bytes(Mode mode, int cap) {
@@ -1136,8 +1233,8 @@ hipError_t configure_kernels(size_t max_dynamic_lds) {
     };
     set((const void*)k_collide_fast<float>);
     set((const void*)k_collide_fast<double>);
-    set((const void*)k_collide_group<float>);
-    set((const void*)k_collide_group<double>);
+    set((const void*)k_collide_bucket<float>);
+    set((const void*)k_collide_bucket<double>);
     set((const void*)k_move_hist<float, true>);
     set((const void*)k_move_hist<float, false>);
     set((const void*)k_move_hist<double, true>);

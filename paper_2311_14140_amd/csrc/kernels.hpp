@@ -17,10 +17,12 @@ struct Work {
     int n_cols;
     const int4* cblocks;    // (instance, first cell, end cell) workgroup-staged collide blocks
     int n_cblocks;
-    const int4* gblocks;    // (instance, first cell, end cell, G) small-cell / FP64-det collide blocks
+    // FP64-det: (instance, first cell, end cell, 64) lane-per-cell collide blocks;
+    // fast modes: (instance, bucket, G, 0) bucket collide blocks
+    const int4* gblocks;
     int n_gblocks;
-    int group_cap;          // particles a small-cell collide workgroup stages in LDS
-    int max_cc;             // largest collision-cell count (LDS of histograms)
+    int group_cap;          // particles a bucket collide workgroup stages in LDS
+    int max_cc;             // largest sort-key count (LDS of histograms)
     int stage_max;          // tiles of at most this many slots are staged in LDS by the scatter
     int fast_cap;           // particles a fast-collide workgroup stages in LDS
 };
@@ -35,7 +37,7 @@ void launch_step_timed(const Work& w, Mode mode, unsigned phase, hipStream_t s, 
 void launch_finalize(const InstDesc* d_desc, int n_inst, hipStream_t s);
 void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s);
 size_t fast_collide_lds_bytes(Mode mode, int cap);
-size_t group_collide_lds_bytes(Mode mode, int cap);
+size_t bucket_collide_lds_bytes(Mode mode, int cap);
 size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max);
 // Allow dynamic LDS up to max_dynamic_lds bytes for the kernels that use it.
 hipError_t configure_kernels(size_t max_dynamic_lds);

@@ -53,7 +53,8 @@ struct Plan {
     int32_t tile_items = 256, tiles = 1, nseg = 1;
     double H = 1.0, lam = 0, dt = 0, g = 0, kntc = 0, crmax0 = 0, sqrt_tw = 1, inv_dy = 0;
     // arena offsets
-    uint64_t off_buf[2][4], off_cell, off_counts, off_segsum, off_count, off_offset, off_crmax,
+    uint64_t off_buf[2][4], off_cell, off_counts, off_segsum, off_kcount, off_koffset, off_count,
+        off_offset, off_crmax,
         off_rem, off_acc, off_ncoll, off_est, off_sc, off_desc, total;
 };
 
@@ -140,6 +141,8 @@ Plan make_plan(const dsmc_params* p) {
     q.off_cell = take((uint64_t)q.N * 4);
     q.off_counts = take((uint64_t)q.tiles * q.Cc * 4);
     q.off_segsum = take((uint64_t)q.nseg * q.Cc * 4);
+    q.off_kcount = take((uint64_t)q.Cc * 4);
+    q.off_koffset = take((uint64_t)q.Cc * 4);
     q.off_count = take((uint64_t)q.Cc * 4);
     q.off_offset = take((uint64_t)q.Cc * 4);
     q.off_crmax = take((uint64_t)q.Cc * 8);
@@ -202,6 +205,8 @@ struct dsmc_handle {
     // array then holds pre-sort cells and the current slot order's cells
     // follow from the counts and offsets
     bool sorted = false;
+    int32_t* bucket_count = nullptr;   // per-bucket count / offset (bucket-sorted launch shapes)
+    int32_t* bucket_offset = nullptr;
     std::string err;
 };
 
@@ -257,6 +262,15 @@ int group_width(double per_cell) {
     return G;
 }
 
+// log2 of the cells per sort bucket of a small-cell instance: the largest
+// power of two of cells holding at most about `target` particles.
+int bucket_shift(double per_cell, int target) {
+    int sh = 0;
+    while ((1 << (sh + 1)) <= kMaxCellsPerKey && (double)(1 << (sh + 1)) * per_cell <= (double)target)
+        ++sh;
+    return sh;
+}
+
 // Order a work list for the XCDs: workgroups are dealt to the 8 XCDs in
 // turn (workgroup p runs on XCD p mod 8), so the list, taken in its natural
 // instance-major order, is cut into 8 contiguous stripes and stripe x is
@@ -305,29 +319,50 @@ int rebuild(dsmc_group* g) {
         dsmc_handle* h = g->members[i];
         InstDesc d = h->desc;
         if (!g->solo) d.phase_mask = DSMC_PHASE_ALL;
+        const double per_cell = (double)d.N / (double)d.Cc;
+        // small cells in a fast mode are sorted by buckets of cells (the
+        // collide kernel finishes the sort); debug phase masks keep the
+        // plain sort by cell
+        const bool bucketed = g->mode != kFp64Det && per_cell < kCoopMin &&
+                              d.phase_mask == (uint32_t)DSMC_PHASE_ALL;
+        int64_t base_items = h->plan.tile_items;
+        if (bucketed) {
+            const int target = g->ppb > 0 ? g->ppb : (g->mode == kFp32Fast ? 2048 : 1024);
+            d.key_shift = bucket_shift(per_cell, target);
+            d.nkeys = (d.Cc + (1 << d.key_shift) - 1) >> d.key_shift;
+            d.kcount = h->bucket_count;
+            d.koffset = h->bucket_offset;
+            // few keys: tiles as large as the scatter can stage
+            base_items = std::max<int64_t>(base_items, stage_slots(h->plan.rb));
+        } else {
+            d.key_shift = 0;
+            d.nkeys = d.Cc;
+            d.kcount = d.count;
+            d.koffset = d.offset;
+        }
         // launch shape: tiles may only grow (the histogram matrix is sized
-        // for the base tile)
+        // for the base tile and all cells)
         const int mult = g->tile_mult > 0 ? g->tile_mult : 1;
-        const int64_t items = std::min<int64_t>((int64_t)h->plan.tile_items * mult,
+        const int64_t items = std::min<int64_t>(base_items * mult,
                                                 (int64_t)std::max(h->plan.N, 1) + kParticleThreads);
         d.tile_items = (int32_t)((items + kParticleThreads - 1) / kParticleThreads * kParticleThreads);
         d.tiles = (d.N + d.tile_items - 1) / d.tile_items;
         d.nseg = (d.tiles + kSegTiles - 1) / kSegTiles;
         descs[i] = d;
         for (int t = 0; t < d.tiles; ++t) tiles.push_back(make_int2(i, t));
-        for (int ch = 0; ch < (d.Cc + kColThreads - 1) / kColThreads; ++ch)
+        for (int ch = 0; ch < (d.nkeys + kColThreads - 1) / kColThreads; ++ch)
             for (int sgi = 0; sgi < d.nseg; ++sgi) cols.push_back(make_int4(i, ch, sgi, 0));
-        max_cc = std::max(max_cc, d.Cc);
-        const double per_cell = (double)d.N / (double)d.Cc;
+        max_cc = std::max(max_cc, d.nkeys);
         if (g->mode == kFp64Det) {
             // one lane per cell, 64 cells per wavefront
             for (int c = 0; c < d.Cc; c += 64) gblocks.push_back(make_int4(i, c, std::min(c + 64, d.Cc), 64));
-        } else if (per_cell < kCoopMin) {
-            // groups of G lanes per cell, one cell per group per pass
-            const int G = group_width(per_cell);
-            const int cpb = (kFastWaves * 64 / G) * (g->ppb > 0 ? std::max(1, g->ppb / 2048) : 1);
-            for (int c = 0; c < d.Cc; c += cpb) gblocks.push_back(make_int4(i, c, std::min(c + cpb, d.Cc), G));
-            const double per_block = per_cell * cpb;
+        } else if (bucketed) {
+            // one workgroup per bucket; groups of G lanes per cell, with G
+            // raised so that a bucket's cells occupy the workgroup's lanes
+            const int cpk = 1 << d.key_shift;
+            const int G = std::min(64, std::max(group_width(per_cell), kFastWaves * 64 / cpk));
+            for (int b = 0; b < d.nkeys; ++b) gblocks.push_back(make_int4(i, b, G, 0));
+            const double per_block = per_cell * cpk;
             group_cap = std::max(group_cap, (int)std::ceil(per_block + 4.0 * std::sqrt(per_block) + 32.0));
         } else {
             const int cpb = auto_cpb(h, g->ppb);
@@ -348,10 +383,10 @@ int rebuild(dsmc_group* g) {
     const size_t fixed = (size_t)kCoopTable * 4 + 1024;  // claim table + static shared
     const int cap_max = (int)(((size_t)max_lds - fixed) / (3 * rb));
     cap = std::min(cap, cap_max);
-    const size_t gfixed = (size_t)kFastWaves * 64 * kGroupTableFactor * 4;
-    group_cap = std::min(group_cap, (int)(((size_t)max_lds - gfixed) / (3 * rb)));
+    const size_t gfixed = bucket_collide_lds_bytes((Mode)g->mode, 0) + 256;  // + static shared
+    group_cap = std::min(group_cap, (int)(((size_t)max_lds - gfixed) / (4 * rb)));
     if ((size_t)max_cc * 4 * kScatterWaves > (size_t)max_lds)
-        return fail(&g->err, DSMC_ERR_INVALID_ARG, "collision cells exceed the LDS tables of the scatter");
+        return fail(&g->err, DSMC_ERR_INVALID_ARG, "sort keys exceed the LDS tables of the scatter");
     // staged scatter for members whose tiles fit, if the LDS can hold it
     int stage_max = stage_slots(rb);
     bool any_staged = false;
@@ -560,6 +595,13 @@ int dsmc_create(const dsmc_params* p, void* stream, void* arena, uint64_t arena_
     d.segsum = (int32_t*)(base + q.off_segsum);
     d.count = (int32_t*)(base + q.off_count);
     d.offset = (int32_t*)(base + q.off_offset);
+    // sorted by cell unless a group's launch shape sorts it by buckets
+    d.nkeys = q.Cc;
+    d.key_shift = 0;
+    d.kcount = d.count;
+    d.koffset = d.offset;
+    h->bucket_count = (int32_t*)(base + q.off_kcount);
+    h->bucket_offset = (int32_t*)(base + q.off_koffset);
     d.crmax = (double*)(base + q.off_crmax);
     d.rem = (double*)(base + q.off_rem);
     d.acc = (double*)(base + q.off_acc);
@@ -963,7 +1005,7 @@ int dsmc_group_autotune(dsmc_group* g, int32_t* tile_mult_out, int32_t* ppb_out)
     int best_tm = 1, best_ppb = 0;
     if (!tune_lookup(sig, &best_tm, &best_ppb)) {
         static const int tms[] = {1, 2, 4};
-        static const int ppbs[] = {0, 2048, 4096};
+        static const int ppbs[] = {0, 1024, 4096};
         hipEvent_t e0, e1;
         HIP_TRY(&g->err, hipEventCreate(&e0));
         HIP_TRY(&g->err, hipEventCreate(&e1));
