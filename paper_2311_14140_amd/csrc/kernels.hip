@@ -1001,20 +1001,112 @@ __device__ __forceinline__ void bucket_sort(const InstDesc& d, const P4<R>& g, i
     __syncthreads();
 }
 
+// Records per lane a bucket-collide workgroup holds in registers while it
+// sorts a bucket (so that all of the bucket's loads are in flight at once).
+template <class R> struct BucketRegs { static constexpr int value = sizeof(R) == 4 ? 12 : 6; };
+
+// The same stable sort with the bucket held in registers (n <= 256 *
+// BucketRegs): every load is issued before the first barrier, velocities go
+// to LDS in cell order and positions straight to their final slots of g (the
+// whole bucket is in registers by then).  Round k of wavefront w covers
+// slots q0 + 64 k + lane of its quarter, the order of bucket_sort.
+template <class R>
+__device__ __forceinline__ void bucket_sort_regs(const InstDesc& d, const P4<R>& g, int s0, int n,
+                                                 int c0, int ncell, int* wt, int* lcnt, int* loff,
+                                                 R* sx, R* sv, R* sz) {
+    constexpr int K = BucketRegs<R>::value;
+    __shared__ int wsum[kFastWaves];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int quarter = ((n + kFastWaves - 1) / kFastWaves + 63) / 64 * 64;
+    const int q0 = min(wv * quarter, n), q1 = min(q0 + quarter, n);
+    int* mine = wt + wv * kMaxCellsPerKey;
+    R ry[K], rx[K], rv[K], rz[K];
+    int lc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = q0 + 64 * k + lane;
+        ry[k] = rx[k] = rv[k] = rz[k] = R(0);
+        if (i < q1) {
+            ry[k] = g.y[s0 + i];
+            rx[k] = g.vx[s0 + i];
+            rv[k] = g.vy[s0 + i];
+            rz[k] = g.vz[s0 + i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        lc[k] = 0;
+        if (q0 + 64 * k + lane < q1) {
+            lc[k] = cell_of<R>(d, ry[k]) - c0;
+            atomicAdd(&mine[lc[k]], 1);
+        }
+    }
+    __syncthreads();
+    const int c = threadIdx.x;
+    int tot = 0;
+    if (c < ncell)
+        for (int q = 0; q < kFastWaves; ++q) tot += wt[q * kMaxCellsPerKey + c];
+    const int incl = wave_incl_scan(tot, lane);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int run = incl - tot;
+    for (int q = 0; q < wv; ++q) run += wsum[q];
+    if (c < ncell) {
+        lcnt[c] = tot;
+        loff[c] = run;
+        for (int q = 0; q < kFastWaves; ++q) {
+            const int v = wt[q * kMaxCellsPerKey + c];
+            wt[q * kMaxCellsPerKey + c] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const unsigned long long lt = lanes_below(lane);
+    const int nbits = ncell > 1 ? 32 - __builtin_clz((unsigned)(ncell - 1)) : 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (q0 + 64 * k < q1) {  // uniform over the wavefront
+            const bool valid = q0 + 64 * k + lane < q1;
+            unsigned long long m = __ballot(valid);
+            for (int b = 0; b < nbits; ++b) {
+                const bool bit = (lc[k] >> b) & 1;
+                const unsigned long long bal = __ballot(bit);
+                m &= bit ? bal : ~bal;
+            }
+            if (valid) {
+                const int pos = mine[lc[k]] + __popcll(m & lt);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if ((m & lt) == 0ull) mine[lc[k]] = pos + __popcll(m);
+                g.y[s0 + pos] = ry[k];
+                sx[pos] = rx[k];
+                sv[pos] = rv[k];
+                sz[pos] = rz[k];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+}
+
 // Collide kernel of bucket-sorted instances: one workgroup per bucket (work
-// item: instance, bucket, G).  The bucket is sorted by cell into LDS (or,
-// when fuller than the staging room, into the same slots of the other
-// particle buffer, which is free during this phase), its cells are collided
-// and sampled there, and the sorted records are written back to the bucket's
-// slots together with each cell's count and offset.
+// item: instance, bucket, G).  The bucket is sorted by cell (velocities into
+// LDS, positions to their final slots), its cells are collided and sampled
+// there, and the velocities are written back to the bucket's slots together
+// with each cell's count and offset.  A bucket fuller than the staging room
+// is sorted into the same slots of the other particle buffer, which is free
+// during this phase, collided there and copied back.  The sort's wavefront
+// tables share LDS with the claim tables, which are set up after the sort.
 template <class R>
 __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDesc* __restrict__ descs,
                                                                    const int4* __restrict__ work,
                                                                    int cap, int do_collide) {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t* claims = (uint32_t*)smem;  // kFastWaves x 64 x kGroupTableFactor entries
-    int* wt = (int*)(claims + kFastWaves * 64 * kGroupTableFactor);
-    int* lcnt = wt + kFastWaves * kMaxCellsPerKey;
+    constexpr int kClaims = kFastWaves * 64 * kGroupTableFactor;
+    static_assert(kFastWaves * kMaxCellsPerKey <= kClaims, "sort tables fit in the claim tables");
+    uint32_t* claims = (uint32_t*)smem;
+    int* wt = (int*)smem;
+    int* lcnt = (int*)(claims + kClaims);
     int* loff = lcnt + kMaxCellsPerKey;
     R* lds = (R*)(loff + kMaxCellsPerKey);
     const int4 w = work[blockIdx.x];
@@ -1025,21 +1117,19 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
     const bool sample = (d.phase_mask & kPhaseSample) && s > d.n_transient;
     const P4<R> g = particles<R>(d, (int)(s & 1));
     const int s0 = d.koffset[b], n = d.kcount[b];
-    for (int i = threadIdx.x; i < kFastWaves * 64 * kGroupTableFactor; i += blockDim.x)
-        claims[i] = 0xFFFFFFFFu;
     for (int i = threadIdx.x; i < kFastWaves * kMaxCellsPerKey; i += blockDim.x) wt[i] = 0;
     __syncthreads();
     uint32_t* wtab = claims + (threadIdx.x >> 6) * 64 * kGroupTableFactor;
-    if (n <= cap) {
-        R* sy = lds;
-        R* sx = lds + cap;
-        R* sv = lds + 2 * cap;
-        R* sz = lds + 3 * cap;
-        bucket_sort<R, R*>(d, g, s0, n, c0, c1 - c0, wt, lcnt, loff, sy, sx, sv, sz);
+    if (n <= cap && n <= kFastWaves * 64 * BucketRegs<R>::value) {
+        R* sx = lds;
+        R* sv = lds + cap;
+        R* sz = lds + 2 * cap;
+        bucket_sort_regs<R>(d, g, s0, n, c0, c1 - c0, wt, lcnt, loff, sx, sv, sz);
+        for (int i = threadIdx.x; i < kClaims; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
+        __syncthreads();
         group_cells<R, R*>(d, (uint32_t)s, c0, c1, lcnt, loff, sx, sv, sz, wtab, G, do_collide, sample);
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            g.y[s0 + i] = sy[i];
             g.vx[s0 + i] = sx[i];
             g.vy[s0 + i] = sv[i];
             g.vz[s0 + i] = sz[i];
@@ -1048,6 +1138,8 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
         const P4<R> o = particles<R>(d, (int)((s - 1) & 1));
         const gptr<R> sy = o.y + s0, sx = o.vx + s0, sv = o.vy + s0, sz = o.vz + s0;
         bucket_sort<R, gptr<R>>(d, g, s0, n, c0, c1 - c0, wt, lcnt, loff, sy, sx, sv, sz);
+        for (int i = threadIdx.x; i < kClaims; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
+        __syncthreads();
         group_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, lcnt, loff, sx, sv, sz, wtab, G, do_collide,
                                 sample);
         __syncthreads();
@@ -1200,7 +1292,7 @@ size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max) {
 size_t bucket_collide_lds_bytes(Mode mode, int cap) {
     const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
     return (size_t)kFastWaves * 64 * kGroupTableFactor * sizeof(uint32_t) +
-           (size_t)(kFastWaves + 2) * kMaxCellsPerKey * sizeof(int) + 4 * (size_t)cap * rb;
+           (size_t)2 * kMaxCellsPerKey * sizeof(int) + 3 * (size_t)cap * rb;
 }
 
 size_t fast_collide_lds_bytes(Mode mode, int cap) {

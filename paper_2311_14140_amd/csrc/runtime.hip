@@ -384,7 +384,7 @@ int rebuild(dsmc_group* g) {
     const int cap_max = (int)(((size_t)max_lds - fixed) / (3 * rb));
     cap = std::min(cap, cap_max);
     const size_t gfixed = bucket_collide_lds_bytes((Mode)g->mode, 0) + 256;  // + static shared
-    group_cap = std::min(group_cap, (int)(((size_t)max_lds - gfixed) / (4 * rb)));
+    group_cap = std::min(group_cap, (int)(((size_t)max_lds - gfixed) / (3 * rb)));
     if ((size_t)max_cc * 4 * kScatterWaves > (size_t)max_lds)
         return fail(&g->err, DSMC_ERR_INVALID_ARG, "sort keys exceed the LDS tables of the scatter");
     // staged scatter for members whose tiles fit, if the LDS can hold it
