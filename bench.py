@@ -37,16 +37,22 @@ MIX_DESC = ("256 instances: Kn log-uniform [0.05, 10], F uniform [0.001, 0.02], 
             "cells uniform [50, 2000], particles/cell uniform [20, 200]")
 
 
-def kernel_bytes(phase: str, N: int, Cc: int, rb: int, coll_frac: float, sampling: bool) -> float:
+def kernel_bytes(phase: str, N: int, Cc: int, rb: int, coll_frac: float, sampling: bool,
+                 bucketed: bool) -> float:
     """Algorithmic HBM bytes of one launch of a phase kernel: the particle
-    record and per-cell traffic the method itself must move (library tables
-    such as per-tile histograms are not counted)."""
-    if phase == "move_hist":   # read y, v; write y, vx and the cell index
-        return N * (4 * rb + 2 * rb + 4)
-    if phase == "scatter":     # read cell + record, write the record
-        return N * (4 + 4 * rb + 4 * rb)
-    if phase == "collide":     # read v, write the collided particles' v; cell tables
-        b = N * 3 * rb + coll_frac * N * 3 * rb + Cc * (8 + 8 + 4 + 4 + 4)
+    record and per-cell traffic its part of the method must move (library
+    tables such as per-tile histograms are not counted).  rb is the bytes of
+    a real; a record is y, vx, vy, vz."""
+    if phase == "count":         # position-only flight: read y, vy
+        return N * 2 * rb
+    if phase == "move_scatter":  # read the record, write it moved to its sorted slot
+        return N * 8 * rb
+    if phase == "collide":
+        if bucketed:             # finishes the sort: read and write the whole record
+            b = N * 8 * rb
+        else:                    # read v, write v back
+            b = N * 6 * rb
+        b += Cc * (8 + 8 + 4 + 4 + 4)  # crmax, rem, count, offset, collisions
         if sampling:
             b += Cc * 12 * 8 * 2
         return b
@@ -264,9 +270,10 @@ def main():
     prof = sub.profile(args.profile_steps)
     kern = {k: prof[k] / args.profile_steps for k in dsmc.Solver.PHASES}
     dom = max(kern, key=kern.get)
-    dom_bytes = kernel_bytes(dom, N, Cc, rb, coll_frac, True)
+    bucketed = rb == 4 and all(p.particles_per_cell / p.n_sub < 256 for p in plist)
+    dom_bytes = kernel_bytes(dom, N, Cc, rb, coll_frac, True, bucketed)
     achieved = dom_bytes / (kern[dom] * 1e-3) / 1e9
-    step_bytes = sum(kernel_bytes(k, N, Cc, rb, coll_frac, True) for k in kern)
+    step_bytes = sum(kernel_bytes(k, N, Cc, rb, coll_frac, True, bucketed) for k in kern)
     log("per-kernel ms/step: " + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()))
     sub.close()
 

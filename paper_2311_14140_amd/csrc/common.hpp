@@ -18,13 +18,17 @@ constexpr int kCoopMin = 256;          // cells this full are collided by a whol
 constexpr int kGroupTableFactor = 16;  // claim-table entries per lane of a small-cell group
 constexpr int kCoopTable = kFastWaves * kClaimTable;  // its claim table (the wave tables together)
 constexpr int kMaxCellsPerKey = 256;   // cells of one sort bucket (a power of two up to this)
+// records per lane the move-scatter holds in registers (FP32, FP64): tiles of
+// bucket-sorted instances are 256 times this many slots
+constexpr int kScatterRegs32 = 6, kScatterRegs64 = 4;
 
 // Scalars an instance keeps on the device so that a step is the same launch
 // sequence every time (and can be replayed from a graph).
 struct DevScalars {
     int64_t step_done;            // steps completed
     int64_t n_sampled;            // sampled steps in the window
-    int32_t status;               // bit 0: non-finite velocity, bit 1: particle count lost
+    int32_t status;               // bit 0: non-finite velocity, bit 1: particle count lost,
+                                  // bit 2: a sorted slot out of range
     int32_t pad_[3];
 };
 

@@ -442,6 +442,253 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
     }
 }
 
+// ------------------------------------------------- count + move-scatter
+// The default step splits the move differently: a particle's new position,
+// and so its cell and sort key, depends only on y, vy and the normal speeds
+// drawn at wall hits (never on vx or vz), so a first pass can histogram the
+// keys of a tile from y and vy alone, without writing anything.  After the
+// scans, k_move_scatter reads each record once, repeats the same move in
+// full (the same arithmetic and draws, so the same key) and writes the moved
+// record straight to its sorted slot.
+
+// Flight of the position alone: the y that move_one would produce.
+template <class R>
+__device__ __forceinline__ R flight_y(const InstDesc& d, uint32_t step, uint32_t slot, R y, R vy) {
+    R vx = R(0), vz = R(0);
+    move_one<R>(d, step, slot, y, vx, vy, vz);
+    return y;
+}
+
+template <class R>
+__global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __restrict__ descs,
+                                                           const int2* __restrict__ work) {
+    extern __shared__ int hist[];
+    const int2 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int nk = d.nkeys;
+    for (int c = threadIdx.x; c < nk; c += blockDim.x) hist[c] = 0;
+    __syncthreads();
+    const int64_t s = d.sc->step_done + 1;
+    const P4<R> b = particles<R>(d, (int)((s - 1) & 1));
+    const int start = w.y * d.tile_items;
+    const int end = min(start + d.tile_items, d.N);
+    constexpr int U = 4;
+    for (int p0 = start + (int)threadIdx.x; p0 < end; p0 += U * kParticleThreads) {
+        R y[U], vy[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 + u * kParticleThreads;
+            y[u] = vy[u] = R(0);
+            if (p < end) {
+                y[u] = b.y[p];
+                vy[u] = b.vy[p];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 + u * kParticleThreads;
+            if (p < end) {
+                const R yn = flight_y<R>(d, (uint32_t)s, (uint32_t)p, y[u], vy[u]);
+                atomicAdd(&hist[cell_of<R>(d, yn) >> d.key_shift], 1);
+            }
+        }
+    }
+    __syncthreads();
+    const gptr<int32_t> row = gmem(d.counts) + (size_t)w.y * nk;
+    for (int c = threadIdx.x; c < nk; c += blockDim.x) row[c] = hist[c];
+}
+
+// Records per lane k_move_scatter holds in registers (tiles up to
+// 256 * this many slots take the one-read path).
+template <class R> struct ScatterRegs {
+    static constexpr int value = sizeof(R) == 4 ? kScatterRegs32 : kScatterRegs64;
+};
+
+// Move and stable scatter of one tile: the same quarter-per-wavefront
+// ranking as k_scatter, with the keys coming from the move.  A tile of at
+// most 256 * ScatterRegs slots is read once into registers, counted from the
+// position-only flight, then moved in full and placed round by round; a
+// larger tile counts its quarters from the position-only flight first and
+// then reads, moves and ranks round by round.  A
+// sorted position outside [0, N) (only possible if the counts and this pass
+// disagreed) is clamped and flagged.
+template <class R>
+__global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDesc* __restrict__ descs,
+                                                                  const int2* __restrict__ work,
+                                                                  int stage_max) {
+    constexpr int K = ScatterRegs<R>::value;
+    extern __shared__ int tables[];  // kScatterWaves x nkeys, then nkeys, then the staging area
+    __shared__ int blk_bad;
+    const int2 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int nk = d.nkeys, shift = d.key_shift;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t s = d.sc->step_done;
+    const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
+    const P4<R> dst = particles<R>(d, (int)(s & 1));
+    const int start = w.y * d.tile_items;
+    const int end = min(start + d.tile_items, d.N);
+    const bool staged = d.tile_items <= stage_max;
+    int* delta = tables + kScatterWaves * nk;
+    int* stage_pos = delta + nk;
+    R* stage_rec = (R*)(tables + (((kScatterWaves + 1) * nk + stage_max + 3) & ~3));
+    for (int k = threadIdx.x; k < kScatterWaves * nk; k += blockDim.x) tables[k] = 0;
+    if (threadIdx.x == 0) blk_bad = 0;
+    const int quarter = (((end - start) + kScatterWaves - 1) / kScatterWaves + 63) / 64 * 64;
+    const int q0 = min(start + wv * quarter, end), q1 = min(q0 + quarter, end);
+    const bool in_regs = quarter <= 64 * K;
+    int* mine = tables + wv * nk;
+    __syncthreads();
+    R ry[K], rx[K], rv[K], rz[K];
+    int key[K];
+    int bad = 0;
+    if (in_regs) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = q0 + 64 * k + lane;
+            ry[k] = rx[k] = rv[k] = rz[k] = R(0);
+            if (i < q1) {
+                ry[k] = src.y[i];
+                rx[k] = src.vx[i];
+                rv[k] = src.vy[i];
+                rz[k] = src.vz[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = q0 + 64 * k + lane;
+            key[k] = 0;
+            if (i < q1) {
+                key[k] = cell_of<R>(d, flight_y<R>(d, (uint32_t)s, (uint32_t)i, ry[k], rv[k])) >> shift;
+                atomicAdd(&mine[key[k]], 1);
+            }
+        }
+    } else {
+        for (int i = q0 + lane; i < q1; i += 64) {
+            const R yn = flight_y<R>(d, (uint32_t)s, (uint32_t)i, src.y[i], src.vy[i]);
+            atomicAdd(&mine[cell_of<R>(d, yn) >> shift], 1);
+        }
+    }
+    __syncthreads();
+    const gptr<int32_t> brow = gmem(d.counts) + (size_t)w.y * nk;
+    for (int c = threadIdx.x; c < nk; c += blockDim.x) {
+        const int b = brow[c];
+        int run = b;
+        for (int q = 0; q < kScatterWaves; ++q) {
+            const int v = tables[q * nk + c];
+            tables[q * nk + c] = run;
+            run += v;
+        }
+        if (staged) delta[c] = run - b;
+    }
+    if (staged) {
+        __shared__ int wsum[kParticleThreads / 64];
+        __syncthreads();
+        const int per = (nk + (int)blockDim.x - 1) / (int)blockDim.x;
+        const int a0 = min((int)threadIdx.x * per, nk), a1 = min(a0 + per, nk);
+        int local = 0;
+        for (int c = a0; c < a1; ++c) local += delta[c];
+        const int incl = wave_incl_scan(local, lane);
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        int run = incl - local;
+        for (int q = 0; q < wv; ++q) run += wsum[q];
+        for (int c = a0; c < a1; ++c) {
+            const int cnt = delta[c];
+            delta[c] = brow[c] - run;
+            run += cnt;
+        }
+    }
+    __syncthreads();
+    const unsigned long long lt = lanes_below(lane);
+    const int nbits = nk > 1 ? 32 - __builtin_clz((unsigned)(nk - 1)) : 0;
+    const int n_tile = end - start;
+    // rank one round of 64 slots and place the records
+    auto place = [&](bool valid, int kk, R y, R vx, R vy, R vz) {
+        unsigned long long m = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (kk >> b) & 1;
+            const unsigned long long bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
+        if (valid) {
+            int pos = mine[kk] + __popcll(m & lt);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if ((m & lt) == 0ull) mine[kk] = pos + __popcll(m);
+            if (staged) {
+                int l = pos - delta[kk];
+                if (l < 0 || l >= n_tile) {
+                    bad |= 2;
+                    l = l < 0 ? 0 : n_tile - 1;
+                }
+                stage_pos[l] = pos;
+                stage_rec[l] = y;
+                stage_rec[stage_max + l] = vx;
+                stage_rec[2 * stage_max + l] = vy;
+                stage_rec[3 * stage_max + l] = vz;
+            } else {
+                if (pos < 0 || pos >= d.N) {
+                    bad |= 2;
+                    pos = pos < 0 ? 0 : d.N - 1;
+                }
+                dst.y[pos] = y;
+                dst.vx[pos] = vx;
+                dst.vy[pos] = vy;
+                dst.vz[pos] = vz;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
+    if (in_regs) {
+        // the full move of each round just before it is placed keeps one
+        // move's temporaries live at a time
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (q0 + 64 * k < q1) {
+                const int i = q0 + 64 * k + lane;
+                const bool valid = i < q1;
+                if (valid) {
+                    move_one<R>(d, (uint32_t)s, (uint32_t)i, ry[k], rx[k], rv[k], rz[k]);
+                    bad |= !(isfinite(rx[k]) && isfinite(rv[k]) && isfinite(rz[k]));
+                }
+                place(valid, key[k], ry[k], rx[k], rv[k], rz[k]);
+            }
+        }
+    } else {
+        for (int base = q0; base < q1; base += 64) {
+            const int i = base + lane;
+            const bool valid = i < q1;
+            R y = R(0), vx = R(0), vy = R(0), vz = R(0);
+            int kk = 0;
+            if (valid) {
+                y = src.y[i];
+                vx = src.vx[i];
+                vy = src.vy[i];
+                vz = src.vz[i];
+                move_one<R>(d, (uint32_t)s, (uint32_t)i, y, vx, vy, vz);
+                bad |= !(isfinite(vx) && isfinite(vy) && isfinite(vz));
+                kk = cell_of<R>(d, y) >> shift;
+            }
+            place(valid, kk, y, vx, vy, vz);
+        }
+    }
+    if (bad) atomicOr(&blk_bad, bad);
+    __syncthreads();
+    if (staged) {
+        for (int l = threadIdx.x; l < n_tile; l += blockDim.x) {
+            int pos = stage_pos[l];
+            if (pos < 0 || pos >= d.N) pos = pos < 0 ? 0 : d.N - 1;  // flagged above
+            dst.y[pos] = stage_rec[l];
+            dst.vx[pos] = stage_rec[stage_max + l];
+            dst.vy[pos] = stage_rec[2 * stage_max + l];
+            dst.vz[pos] = stage_rec[3 * stage_max + l];
+        }
+    }
+    // error path only: bit 0 a non-finite velocity, bit 2 a slot out of range
+    if (threadIdx.x == 0 && blk_bad) atomicOr(&d.sc->status, (blk_bad & 1) | ((blk_bad & 2) << 1));
+}
+
 // Debug path without sorting: the next buffer is a copy of the current one.
 template <class R>
 __global__ __launch_bounds__(kParticleThreads) void k_copy(const InstDesc* __restrict__ descs,
@@ -1226,13 +1473,12 @@ __global__ __launch_bounds__(256) void k_reset_window(const InstDesc* __restrict
     if (threadIdx.x == 0) d.sc->n_sampled = 0;
 }
 
-template <class R>
-void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipEvent_t* ev = nullptr) {
+// The kernels of one step under a debug phase mask (a move without the sort,
+// a sort without a move, or neither): the move writes the cell index array in
+// place, and the sort (if any) is a separate stable scatter from that array.
+template <class R, class Mark>
+void step_kernels_debug(const Work& w, Mode mode, unsigned phase, hipStream_t st, Mark mark) {
     const size_t hist_lds = (size_t)w.max_cc * sizeof(int);
-    auto mark = [&](int i) {
-        if (ev) (void)hipEventRecord(ev[i], st);
-    };
-    mark(0);
     if (phase & (kPhaseMove | kPhaseSort)) {
         if (phase & kPhaseMove)
             hipLaunchKernelGGL((k_move_hist<R, true>), dim3(w.n_tiles), dim3(kParticleThreads),
@@ -1259,6 +1505,31 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
         mark(4);
         hipLaunchKernelGGL((k_copy<R>), dim3(w.n_tiles), dim3(kParticleThreads), 0, st, w.desc,
                            w.tiles);
+    }
+}
+
+template <class R>
+void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipEvent_t* ev = nullptr) {
+    const size_t hist_lds = (size_t)w.max_cc * sizeof(int);
+    auto mark = [&](int i) {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    if ((phase & kPhaseMove) && (phase & kPhaseSort)) {
+        hipLaunchKernelGGL((k_count<R>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds, st, w.desc,
+                           w.tiles);
+        mark(1);
+        hipLaunchKernelGGL(k_colsum, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
+        mark(2);
+        hipLaunchKernelGGL(k_scan, dim3(w.n_inst), dim3(kScanThreads), 0, st, w.desc, 1);
+        mark(3);
+        hipLaunchKernelGGL(k_colprefix, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
+        mark(4);
+        hipLaunchKernelGGL((k_move_scatter<R>), dim3(w.n_tiles), dim3(kParticleThreads),
+                           scatter_lds_bytes(mode, w.max_cc, w.stage_max), st, w.desc, w.tiles,
+                           w.stage_max);
+    } else {
+        step_kernels_debug<R>(w, mode, phase, st, mark);
     }
     mark(5);
     if (phase & (kPhaseCollide | kPhaseSample)) {
@@ -1333,6 +1604,10 @@ hipError_t configure_kernels(size_t max_dynamic_lds) {
     set((const void*)k_move_hist<double, false>);
     set((const void*)k_scatter<float>);
     set((const void*)k_scatter<double>);
+    set((const void*)k_count<float>);
+    set((const void*)k_count<double>);
+    set((const void*)k_move_scatter<float>);
+    set((const void*)k_move_scatter<double>);
     return e;
 }
 

@@ -80,6 +80,13 @@ int base_items_per_thread(int32_t N, int32_t Cc, size_t rb) {
     return k;
 }
 
+// Instances whose fast-mode steps sort by buckets of cells (the collide
+// kernel finishes the sort): fewer than kCoopMin particles per collision cell.
+bool bucket_eligible(const dsmc_params* p) {
+    return p->precision != DSMC_FP64_DETERMINISTIC &&
+           (double)p->particles_per_cell / (double)p->n_sub < (double)kCoopMin;
+}
+
 int check_params(const dsmc_params* p, std::string* err) {
     if (!p) return fail(err, DSMC_ERR_INVALID_ARG, "params is NULL");
     if (p->struct_size != sizeof(dsmc_params))
@@ -125,7 +132,12 @@ Plan make_plan(const dsmc_params* p) {
     q.crmax0 = 5.0 * std::sqrt(2.0 * p->wall_temperature);
     q.sqrt_tw = std::sqrt(p->wall_temperature);
     q.inv_dy = (double)q.Cc / q.H;
-    const int k = base_items_per_thread(q.N, q.Cc, q.rb);
+    int k = base_items_per_thread(q.N, q.Cc, q.rb);
+    if (bucket_eligible(p)) {
+        // few sort keys: tiles as large as the move-scatter holds in registers
+        const int regs = q.rb == 4 ? kScatterRegs32 : kScatterRegs64;
+        k = std::max(1, std::min(regs, (q.N + kParticleThreads - 1) / kParticleThreads));
+    }
     q.tile_items = k * kParticleThreads;
     q.tiles = (q.N + q.tile_items - 1) / q.tile_items;
     q.nseg = (q.tiles + kSegTiles - 1) / kSegTiles;
@@ -332,8 +344,6 @@ int rebuild(dsmc_group* g) {
             d.nkeys = (d.Cc + (1 << d.key_shift) - 1) >> d.key_shift;
             d.kcount = h->bucket_count;
             d.koffset = h->bucket_offset;
-            // few keys: tiles as large as the scatter can stage
-            base_items = std::max<int64_t>(base_items, stage_slots(h->plan.rb));
         } else {
             d.key_shift = 0;
             d.nkeys = d.Cc;
@@ -479,6 +489,7 @@ int sync_check(dsmc_handle* h) {
     HIP_TRY(&h->err, hipMemcpy(&sc, h->desc.sc, sizeof sc, hipMemcpyDeviceToHost));
     if (sc.status & 1) return fail(&h->err, DSMC_ERR_NUMERIC, "non-finite particle velocity");
     if (sc.status & 2) return fail(&h->err, DSMC_ERR_NUMERIC, "cell counts do not add up to N");
+    if (sc.status & 4) return fail(&h->err, DSMC_ERR_NUMERIC, "sorted slot out of range");
     return DSMC_OK;
 }
 

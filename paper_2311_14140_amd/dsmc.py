@@ -233,7 +233,11 @@ class Solver:
             arrs["raw"] = rawa
         return arrs
 
-    PHASES = ("move_hist", "colsum", "scan", "colprefix", "scatter", "collide")
+    # kernel slots of a step: the key histogram (position-only flight), the
+    # three column-scan kernels, the move with the stable scatter, and the
+    # collide with fused sampling (under a debug phase mask the first and
+    # fifth slots are the in-place move and the plain scatter)
+    PHASES = ("count", "colsum", "scan", "colprefix", "move_scatter", "collide")
 
     def profile(self, n_steps: int) -> dict:
         """Device milliseconds per kernel over n_steps eagerly launched steps."""
