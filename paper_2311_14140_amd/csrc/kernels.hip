@@ -1020,7 +1020,7 @@ __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int
                 for (int k = 0; k < kMoments; ++k) {
                     double t = sh.mom[0][k];
                     for (int q = 1; q < nw; ++q) t += sh.mom[q][k];
-                    a[k] += t;
+                    unsafeAtomicAdd(&a[k], t);  // one writer per cell: no read needed
                 }
             }
             __syncthreads();
@@ -1078,10 +1078,14 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
 // of its own in LDS; the group then reduces the cell's sampling sums.  The
 // groups of a wavefront run in lockstep, so a round needs no barrier.  Cell
 // c of [c0, c1) holds lcnt[c - c0] particles from index loff[c - c0] of the
-// velocity arrays.
+// velocity arrays; lcrm / lrem hold copies of its crmax and remainder, read
+// before the sort so that their latency hides behind it.  Each cell has one
+// writer, so its counters and accumulators are updated with atomics that
+// return nothing (the same sums as a read-modify-write, without the wait).
 template <class R, class V>
 __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c0, int c1,
-                                            const int* lcnt, const int* loff, V vx, V vy, V vz,
+                                            const int* lcnt, const int* loff, const double* lcrm,
+                                            const double* lrem, V vx, V vy, V vz,
                                             uint32_t* wtab, int G, bool do_collide, bool sample) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int ngw = 64 / G;
@@ -1101,8 +1105,8 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
             nc = lcnt[c - c0];
             o = loff[c - c0];
             if (do_collide && nc >= 2) {
-                crm0 = d.crmax[c];
-                mreal = (((0.5 * (double)nc) * (double)(nc - 1)) * crm0) * d.kntc + d.rem[c];
+                crm0 = lcrm[c - c0];
+                mreal = (((0.5 * (double)nc) * (double)(nc - 1)) * crm0) * d.kntc + lrem[c - c0];
                 mf = floor(mreal);
                 M = (int64_t)mf;
             }
@@ -1163,12 +1167,12 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
             if (do_collide && nc >= 2) {
                 d.rem[c] = mreal - mf;
                 if (mx > crm0) d.crmax[c] = mx;
-                d.ncoll[c] += cc;
+                if (cc) atomicAdd(&d.ncoll[c], cc);
             }
             if (sample) {
                 double* a = d.acc + (size_t)c * kMoments;
 #pragma unroll
-                for (int k = 0; k < kMoments; ++k) a[k] += m.s[k];
+                for (int k = 0; k < kMoments; ++k) unsafeAtomicAdd(&a[k], m.s[k]);
             }
         }
     }
@@ -1353,7 +1357,9 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
     static_assert(kFastWaves * kMaxCellsPerKey <= kClaims, "sort tables fit in the claim tables");
     uint32_t* claims = (uint32_t*)smem;
     int* wt = (int*)smem;
-    int* lcnt = (int*)(claims + kClaims);
+    double* lcrm = (double*)(claims + kClaims);
+    double* lrem = lcrm + kMaxCellsPerKey;
+    int* lcnt = (int*)(lrem + kMaxCellsPerKey);
     int* loff = lcnt + kMaxCellsPerKey;
     R* lds = (R*)(loff + kMaxCellsPerKey);
     const int4 w = work[blockIdx.x];
@@ -1365,6 +1371,11 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
     const P4<R> g = particles<R>(d, (int)(s & 1));
     const int s0 = d.koffset[b], n = d.kcount[b];
     for (int i = threadIdx.x; i < kFastWaves * kMaxCellsPerKey; i += blockDim.x) wt[i] = 0;
+    if (do_collide)
+        for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
+            lcrm[c - c0] = d.crmax[c];
+            lrem[c - c0] = d.rem[c];
+        }
     __syncthreads();
     uint32_t* wtab = claims + (threadIdx.x >> 6) * 64 * kGroupTableFactor;
     if (n <= cap && n <= kFastWaves * 64 * BucketRegs<R>::value) {
@@ -1374,7 +1385,8 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
         bucket_sort_regs<R>(d, g, s0, n, c0, c1 - c0, wt, lcnt, loff, sx, sv, sz);
         for (int i = threadIdx.x; i < kClaims; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
         __syncthreads();
-        group_cells<R, R*>(d, (uint32_t)s, c0, c1, lcnt, loff, sx, sv, sz, wtab, G, do_collide, sample);
+        group_cells<R, R*>(d, (uint32_t)s, c0, c1, lcnt, loff, lcrm, lrem, sx, sv, sz, wtab, G,
+                           do_collide, sample);
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             g.vx[s0 + i] = sx[i];
@@ -1387,8 +1399,8 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
         bucket_sort<R, gptr<R>>(d, g, s0, n, c0, c1 - c0, wt, lcnt, loff, sy, sx, sv, sz);
         for (int i = threadIdx.x; i < kClaims; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
         __syncthreads();
-        group_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, lcnt, loff, sx, sv, sz, wtab, G, do_collide,
-                                sample);
+        group_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, lcnt, loff, lcrm, lrem, sx, sv, sz, wtab, G,
+                                do_collide, sample);
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             g.y[s0 + i] = sy[i];
@@ -1563,7 +1575,7 @@ size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max) {
 size_t bucket_collide_lds_bytes(Mode mode, int cap) {
     const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
     return (size_t)kFastWaves * 64 * kGroupTableFactor * sizeof(uint32_t) +
-           (size_t)2 * kMaxCellsPerKey * sizeof(int) + 3 * (size_t)cap * rb;
+           (size_t)2 * kMaxCellsPerKey * (sizeof(double) + sizeof(int)) + 3 * (size_t)cap * rb;
 }
 
 size_t fast_collide_lds_bytes(Mode mode, int cap) {
