@@ -1422,53 +1422,59 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
 // <|c|^2 c_a> from the raw moments; q_a = nu <|c|^2 c_a>/2; mass flow
 // Q = sum S1_x/(K N).  Velocities, heat fluxes and Q are divided by
 // v0 = sqrt(2) and stresses are over n kT: the dimensionless variables of
-// Eq. 6.
+// Eq. 6.  The sum of Q runs in cell order: all threads stage the cells'
+// x-momentum sums in LDS and one thread adds them in order.
 __global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ descs) {
+    constexpr int kChunk = 2048;  // sampling cells whose x-momentum sums are staged at a time
+    __shared__ double col[kChunk];
+    __shared__ unsigned long long coll_part[256];
     const InstDesc& d = descs[blockIdx.x];
     const int C = d.C, ns = d.n_sub;
     const double K = (double)d.sc->n_sampled, N = (double)d.N;
     const double v0 = __builtin_sqrt(2.0);
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        double s[kMoments];
-        for (int m = 0; m < kMoments; ++m) s[m] = 0.0;
-        for (int k = 0; k < ns; ++k) {
-            const double* a = d.acc + ((size_t)c * ns + k) * kMoments;
-            for (int m = 0; m < kMoments; ++m) s[m] += a[m];
+    double q = 0.0;  // only thread 0's copy is used: the sum in cell order
+    for (int cs = 0; cs < C; cs += kChunk) {
+        const int ce = min(cs + kChunk, C);
+        for (int c = cs + (int)threadIdx.x; c < ce; c += blockDim.x) {
+            double s[kMoments];
+            for (int m = 0; m < kMoments; ++m) s[m] = 0.0;
+            for (int k = 0; k < ns; ++k) {
+                const double* a = d.acc + ((size_t)c * ns + k) * kMoments;
+                for (int m = 0; m < kMoments; ++m) s[m] += a[m];
+            }
+            col[c - cs] = s[1];
+            const double n_c = (s[0] * (double)C) / (K * N);
+            const double u = s[1] / s[0], v = s[2] / s[0], ww = s[3] / s[0];
+            const double mxx = s[4] / s[0] - u * u;
+            const double myy = s[5] / s[0] - v * v;
+            const double mzz = s[6] / s[0] - ww * ww;
+            const double mxy = s[7] / s[0] - u * v;
+            const double trace2 = (s[4] + s[5]) + s[6];
+            const double usq = (u * u + v * v) + ww * ww;
+            const double cx = ((s[10] / s[0] - u * (trace2 / s[0])) -
+                               2.0 * (((u * s[4] + v * s[7]) + ww * s[8]) / s[0])) + 2.0 * u * usq;
+            const double cy = ((s[11] / s[0] - v * (trace2 / s[0])) -
+                               2.0 * (((u * s[7] + v * s[5]) + ww * s[9]) / s[0])) + 2.0 * v * usq;
+            double* e = d.est;
+            e[0 * C + c] = n_c;
+            e[1 * C + c] = u / v0;
+            e[2 * C + c] = v / v0;
+            e[3 * C + c] = ww / v0;
+            e[4 * C + c] = ((mxx + myy) + mzz) / 3.0;
+            e[5 * C + c] = n_c * mxy;
+            e[6 * C + c] = (0.5 * n_c * cx) / v0;
+            e[7 * C + c] = (0.5 * n_c * cy) / v0;
         }
-        const double n_c = (s[0] * (double)C) / (K * N);
-        const double u = s[1] / s[0], v = s[2] / s[0], ww = s[3] / s[0];
-        const double mxx = s[4] / s[0] - u * u;
-        const double myy = s[5] / s[0] - v * v;
-        const double mzz = s[6] / s[0] - ww * ww;
-        const double mxy = s[7] / s[0] - u * v;
-        const double trace2 = (s[4] + s[5]) + s[6];
-        const double usq = (u * u + v * v) + ww * ww;
-        const double cx = ((s[10] / s[0] - u * (trace2 / s[0])) -
-                           2.0 * (((u * s[4] + v * s[7]) + ww * s[8]) / s[0])) + 2.0 * u * usq;
-        const double cy = ((s[11] / s[0] - v * (trace2 / s[0])) -
-                           2.0 * (((u * s[7] + v * s[5]) + ww * s[9]) / s[0])) + 2.0 * v * usq;
-        double* e = d.est;
-        e[0 * C + c] = n_c;
-        e[1 * C + c] = u / v0;
-        e[2 * C + c] = v / v0;
-        e[3 * C + c] = ww / v0;
-        e[4 * C + c] = ((mxx + myy) + mzz) / 3.0;
-        e[5 * C + c] = n_c * mxy;
-        e[6 * C + c] = (0.5 * n_c * cx) / v0;
-        e[7 * C + c] = (0.5 * n_c * cy) / v0;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int c = 0; c < ce - cs; ++c) q += col[c];
+        __syncthreads();
     }
-    __shared__ unsigned long long coll_part[256];
     unsigned long long cs = 0;
     for (int c = threadIdx.x; c < d.Cc; c += blockDim.x) cs += d.ncoll[c];
     coll_part[threadIdx.x] = cs;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double q = 0.0;
-        for (int c = 0; c < C; ++c) {
-            double sx = 0.0;
-            for (int k = 0; k < ns; ++k) sx += d.acc[((size_t)c * ns + k) * kMoments + 1];
-            q += sx;
-        }
         unsigned long long tot = 0;
         for (int t = 0; t < (int)blockDim.x; ++t) tot += coll_part[t];
         d.est[kEstPerCell * C] = (q / (K * N)) / v0;
