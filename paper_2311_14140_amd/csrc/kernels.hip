@@ -103,7 +103,75 @@ __global__ void k_init(const InstDesc* __restrict__ descs) {
 // segment; whenever the particle reaches a plate before its time runs out it
 // is re-emitted from the wall Maxwellian at T_w (normal speed
 // sqrt(-2 T_w ln U), tangential components a polar normal pair), which may
-// happen several times in one step.  Returns the number of wall hits.
+// happen several times in one step.  flight_start and flight_from_wall split
+// the flight at the first plate contact, so that a kernel can run the rare
+// re-emissions apart from the straight flights; move_one is the same flight
+// as one loop, in the same arithmetic (both forms are checked bit for bit
+// against the sequential reference by the FP64 tests).
+
+// Time until the particle reaches the plate it moves towards (infinite when
+// it moves parallel to the plates).
+template <class R> __device__ __forceinline__ R time_to_wall(const InstDesc& d, R y, R vy) {
+    const R H = (R)d.H;
+    if (vy > R(0)) return (H - y) / vy;
+    if (vy < R(0)) return (R(0) - y) / vy;
+    return (R)INFINITY;
+}
+
+// The first segment: when no plate is reached within dt the particle flies
+// straight (returns true); otherwise the state is left as it is and the
+// plate (top or not) and the time left when it is reached are returned.
+template <class R>
+__device__ __forceinline__ bool flight_start(const InstDesc& d, R& y, R& vx, R vy, R& t_left,
+                                             bool& top) {
+    const R H = (R)d.H, g = (R)d.g, t = (R)d.dt;
+    const R tw = time_to_wall<R>(d, y, vy);
+    if (tw >= t) {
+        y = y + vy * t;
+        vx = vx + g * t;
+        if (y < R(0)) y = R(0);
+        if (y > H) y = H;
+        return true;
+    }
+    top = vy > R(0);
+    t_left = t - tw;
+    return false;
+}
+
+// The rest of a flight from the moment the particle reaches a plate with time
+// t left: re-emission, further flight and any later hits (draw h of the
+// particle's wall stream at its h-th hit).  The incoming y, vx, vy, vz are
+// not read.  Returns the number of hits.
+template <class R>
+__device__ __forceinline__ int flight_from_wall(const InstDesc& d, uint32_t step, uint32_t slot,
+                                                bool top, R t, R& y, R& vx, R& vy, R& vz) {
+    const R H = (R)d.H, g = (R)d.g, sd = (R)d.sqrt_tw;
+    int h = 0;
+    for (;;) {
+        y = top ? H : R(0);
+        Stream st(d.key0, d.key1, step, slot, (uint32_t)h, kTagWall);
+        R ua, ub;
+        Num<R>::uni2(st.next(), ua, ub);
+        const R vn = Num<R>::sqrt(R(-2) * Num<R>::log(ua)) * sd;
+        normal_pair<R>(st, sd, vx, vz);
+        vy = top ? -vn : vn;
+        ++h;
+        const R tw = time_to_wall<R>(d, y, vy);
+        if (tw >= t) {
+            y = y + vy * t;
+            vx = vx + g * t;
+            break;
+        }
+        top = vy > R(0);
+        t = t - tw;
+    }
+    if (y < R(0)) y = R(0);
+    if (y > H) y = H;
+    return h;
+}
+
+// The whole flight of one step as one loop (the same arithmetic as
+// flight_start followed by flight_from_wall).  Returns the number of hits.
 template <class R>
 __device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32_t slot, R& y,
                                         R& vx, R& vy, R& vz) {
@@ -111,13 +179,7 @@ __device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32
     R t = (R)d.dt;
     int h = 0;
     for (;;) {
-        R tw;
-        if (vy > R(0))
-            tw = (H - y) / vy;
-        else if (vy < R(0))
-            tw = (R(0) - y) / vy;
-        else
-            tw = (R)INFINITY;
+        const R tw = time_to_wall<R>(d, y, vy);
         if (tw >= t) {
             y = y + vy * t;
             vx = vx + g * t;
@@ -506,9 +568,9 @@ template <class R> struct ScatterRegs {
 
 // Move and stable scatter of one tile: the same quarter-per-wavefront
 // ranking as k_scatter, with the keys coming from the move.  A tile of at
-// most 256 * ScatterRegs slots is read once into registers, counted from the
-// position-only flight, then moved in full and placed round by round; a
-// larger tile counts its quarters from the position-only flight first and
+// most 256 * ScatterRegs slots is read once into registers, moved (wall
+// re-emissions queued and run together), counted and placed round by round;
+// a larger tile counts its quarters from the position-only flight first and
 // then reads, moves and ranks round by round.  A
 // sorted position outside [0, N) (only possible if the counts and this pass
 // disagreed) is clamped and flagged.
@@ -554,12 +616,72 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
                 rz[k] = src.vz[i];
             }
         }
+        // Straight flights at once; records that reach a plate are queued
+        // in this wavefront's share of the (not yet used) staging area and
+        // re-emitted together, 64 at a time, instead of once per round in
+        // which any lane hits.  Queue overflow is handled in place.
+        const int qcap = staged ? stage_max / 5 : 0;
+        int* qslot = stage_pos + wv * (stage_max / 4);
+        R* qt = stage_rec + wv * stage_max;
+        R* qy = qt + qcap;
+        R* qx = qy + qcap;
+        R* qv = qx + qcap;
+        R* qz = qv + qcap;
+        int nq = 0, jq[K];
+        unsigned hitm = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = q0 + 64 * k + lane;
+            bool hit = false, top = false;
+            R tl = R(0);
+            jq[k] = 0;
+            if (i < q1) hit = !flight_start<R>(d, ry[k], rx[k], rv[k], tl, top);
+            const unsigned long long hm = __ballot(hit);
+            if (hit) {
+                const int j = nq + __popcll(hm & lanes_below(lane));
+                if (j < qcap) {
+                    qslot[j] = i;
+                    qt[j] = top ? tl : -tl;  // the time left is > 0; its sign keeps the plate
+                    jq[k] = j;
+                    hitm |= 1u << k;
+                } else {
+                    flight_from_wall<R>(d, (uint32_t)s, (uint32_t)i, top, tl, ry[k], rx[k], rv[k], rz[k]);
+                }
+            }
+            nq += __popcll(hm);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int nproc = min(nq, qcap);
+        for (int b0 = 0; b0 < nproc; b0 += 64) {
+            const int j = b0 + lane;
+            if (j < nproc) {
+                const R tt = qt[j];
+                R y = R(0), vx = R(0), vy = R(0), vz = R(0);
+                flight_from_wall<R>(d, (uint32_t)s, (uint32_t)qslot[j], tt > R(0), tt > R(0) ? tt : -tt,
+                                    y, vx, vy, vz);
+                qy[j] = y;
+                qx[j] = vx;
+                qv[j] = vy;
+                qz[j] = vz;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = q0 + 64 * k + lane;
             key[k] = 0;
+            if ((hitm >> k) & 1u) {
+                const int j = jq[k];
+                ry[k] = qy[j];
+                rx[k] = qx[j];
+                rv[k] = qv[j];
+                rz[k] = qz[j];
+            }
             if (i < q1) {
-                key[k] = cell_of<R>(d, flight_y<R>(d, (uint32_t)s, (uint32_t)i, ry[k], rv[k])) >> shift;
+                bad |= !(isfinite(rx[k]) && isfinite(rv[k]) && isfinite(rz[k]));
+                key[k] = cell_of<R>(d, ry[k]) >> shift;
                 atomicAdd(&mine[key[k]], 1);
             }
         }
@@ -641,20 +763,9 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
         __builtin_amdgcn_wave_barrier();
     };
     if (in_regs) {
-        // the full move of each round just before it is placed keeps one
-        // move's temporaries live at a time
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (q0 + 64 * k < q1) {
-                const int i = q0 + 64 * k + lane;
-                const bool valid = i < q1;
-                if (valid) {
-                    move_one<R>(d, (uint32_t)s, (uint32_t)i, ry[k], rx[k], rv[k], rz[k]);
-                    bad |= !(isfinite(rx[k]) && isfinite(rv[k]) && isfinite(rz[k]));
-                }
-                place(valid, key[k], ry[k], rx[k], rv[k], rz[k]);
-            }
-        }
+        for (int k = 0; k < K; ++k)
+            if (q0 + 64 * k < q1) place(q0 + 64 * k + lane < q1, key[k], ry[k], rx[k], rv[k], rz[k]);
     } else {
         for (int base = q0; base < q1; base += 64) {
             const int i = base + lane;
