@@ -19,19 +19,15 @@ namespace dsmc {
 
 enum : uint32_t { kTagInit = 1u, kTagWall = 2u, kTagColl = 3u, kTagRound = 4u };
 
-__host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __umulhi(a, b);
-#else
-    return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
-#endif
-}
-
 __host__ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a = 0xD2511F53u * c.x, ah = mulhi32(0xD2511F53u, c.x);
-        const uint32_t b = 0xCD9E8D57u * c.z, bh = mulhi32(0xCD9E8D57u, c.z);
+        // each 32x32->64 product as one 64-bit multiply (one v_mad_u64_u32
+        // on the device instead of separate low and high multiplies)
+        const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        const uint32_t a = (uint32_t)pa, ah = (uint32_t)(pa >> 32);
+        const uint32_t b = (uint32_t)pb, bh = (uint32_t)(pb >> 32);
         c = make_uint4(bh ^ c.y ^ k0, b, ah ^ c.w ^ k1, a);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
