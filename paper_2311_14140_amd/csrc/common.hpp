@@ -15,9 +15,9 @@ constexpr int kSegTiles = 32;          // tiles per column-scan segment
 constexpr int kClaimTable = 1024;      // per-wavefront claim table of the fast collide
 constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
 constexpr int kCoopMin = 256;          // cells this full are collided by a whole workgroup
-constexpr int kGroupTableFactor = 16;  // claim-table entries per lane of a small-cell group
+constexpr int kGroupTableFactor = 8;   // claim-table entries per lane of a small-cell group
 constexpr int kCoopTable = kFastWaves * kClaimTable;  // its claim table (the wave tables together)
-constexpr int kMaxCellsPerKey = 256;   // cells of one sort bucket (a power of two up to this)
+constexpr int kMaxCellsPerKey = 128;   // cells of one sort bucket (a power of two up to this)
 // records per lane the move-scatter holds in registers (FP32, FP64): tiles of
 // bucket-sorted instances are 256 times this many slots
 constexpr int kScatterRegs32 = 6, kScatterRegs64 = 4;
