@@ -68,7 +68,7 @@ struct InstDesc {
     int32_t* offset;   // Cc
     double* crmax;     // Cc
     double* rem;       // Cc
-    double* acc;       // Cc * kMoments
+    double* acc;       // kMoments * Cc, moment-major: moment k of cell c at k * Cc + c
     uint32_t* ncoll;   // Cc: accepted collisions in the window, per collision cell
     double* est;       // kEstPerCell * C + 3 (mass flow, sampled steps, collisions)
     DevScalars* sc;

@@ -89,7 +89,7 @@ __global__ void k_init(const InstDesc* __restrict__ descs) {
         d.count[p] = 0;
         d.offset[p] = 0;
         d.ncoll[p] = 0u;
-        for (int m = 0; m < kMoments; ++m) d.acc[(size_t)p * kMoments + m] = 0.0;
+        for (int m = 0; m < kMoments; ++m) d.acc[(size_t)m * d.Cc + p] = 0.0;
     }
     if (p == 0) {
         d.sc->step_done = 0;
@@ -912,9 +912,9 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
             Mom m;
             mom_zero(m);
             for (int q = 0; q < n; ++q) mom_add(m, vx[q], vy[q], vz[q]);
-            double* a = d.acc + (size_t)c * kMoments;
+            double* a = d.acc + c;  // moment k of cell c at k * Cc + c
 #pragma unroll
-            for (int k = 0; k < kMoments; ++k) a[k] += m.s[k];
+            for (int k = 0; k < kMoments; ++k) a[(size_t)k * d.Cc] += m.s[k];
         }
     }
 }
@@ -1127,11 +1127,11 @@ __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int
                 for (int k = 0; k < kMoments; ++k) sh.mom[wv][k] = tot[k];
             __syncthreads();
             if (threadIdx.x == 0) {
-                double* a = d.acc + (size_t)c * kMoments;
+                double* a = d.acc + c;
                 for (int k = 0; k < kMoments; ++k) {
                     double t = sh.mom[0][k];
                     for (int q = 1; q < nw; ++q) t += sh.mom[q][k];
-                    unsafeAtomicAdd(&a[k], t);  // one writer per cell: no read needed
+                    unsafeAtomicAdd(&a[(size_t)k * d.Cc], t);  // one writer per cell: no read needed
                 }
             }
             __syncthreads();
@@ -1281,9 +1281,9 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
                 if (cc) atomicAdd(&d.ncoll[c], cc);
             }
             if (sample) {
-                double* a = d.acc + (size_t)c * kMoments;
+                double* a = d.acc + c;
 #pragma unroll
-                for (int k = 0; k < kMoments; ++k) unsafeAtomicAdd(&a[k], m.s[k]);
+                for (int k = 0; k < kMoments; ++k) unsafeAtomicAdd(&a[(size_t)k * d.Cc], m.s[k]);
             }
         }
     }
@@ -1550,8 +1550,8 @@ __global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ d
             double s[kMoments];
             for (int m = 0; m < kMoments; ++m) s[m] = 0.0;
             for (int k = 0; k < ns; ++k) {
-                const double* a = d.acc + ((size_t)c * ns + k) * kMoments;
-                for (int m = 0; m < kMoments; ++m) s[m] += a[m];
+                const double* a = d.acc + ((size_t)c * ns + k);
+                for (int m = 0; m < kMoments; ++m) s[m] += a[(size_t)m * d.Cc];
             }
             col[c - cs] = s[1];
             const double n_c = (s[0] * (double)C) / (K * N);

@@ -684,7 +684,12 @@ int dsmc_sample(dsmc_handle* h, dsmc_moments* out, int reset_window) {
     double* dst[kEstPerCell] = {out->n, out->ux, out->uy, out->uz, out->T, out->pxy, out->qx, out->qy};
     for (int m = 0; m < kEstPerCell; ++m)
         if (dst[m]) std::memcpy(dst[m], est.data() + (size_t)m * C, sizeof(double) * C);
-    if (out->raw_sums) std::memcpy(out->raw_sums, raw.data(), raw.size() * sizeof(double));
+    if (out->raw_sums) {
+        // device layout is moment-major; the ABI's is 12 sums per collision cell
+        const size_t cc = (size_t)h->plan.Cc;
+        for (size_t c = 0; c < cc; ++c)
+            for (int k = 0; k < kMoments; ++k) out->raw_sums[c * kMoments + k] = raw[(size_t)k * cc + c];
+    }
     out->mass_flow = sc.n_sampled ? est[(size_t)kEstPerCell * C] : NAN;
     out->n_sampled_steps = sc.n_sampled;
     out->n_collisions = (int64_t)est[(size_t)kEstPerCell * C + 2];
