@@ -600,6 +600,11 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
     const int q0 = min(start + wv * quarter, end), q1 = min(q0 + quarter, end);
     const bool in_regs = quarter <= 64 * K;
     int* mine = tables + wv * nk;
+    // the tile's scatter bases, read now so that their latency hides behind
+    // the move (thread c holds key c's base when there are at most 256 keys)
+    const gptr<int32_t> brow = gmem(d.counts) + (size_t)w.y * nk;
+    const int my_base = (int)threadIdx.x < nk ? (int)brow[threadIdx.x] : 0;
+    auto base_of = [&](int c) { return c == (int)threadIdx.x ? my_base : (int)brow[c]; };
     __syncthreads();
     R ry[K], rx[K], rv[K], rz[K];
     int key[K];
@@ -692,9 +697,8 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
         }
     }
     __syncthreads();
-    const gptr<int32_t> brow = gmem(d.counts) + (size_t)w.y * nk;
     for (int c = threadIdx.x; c < nk; c += blockDim.x) {
-        const int b = brow[c];
+        const int b = base_of(c);
         int run = b;
         for (int q = 0; q < kScatterWaves; ++q) {
             const int v = tables[q * nk + c];
@@ -717,7 +721,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
         for (int q = 0; q < wv; ++q) run += wsum[q];
         for (int c = a0; c < a1; ++c) {
             const int cnt = delta[c];
-            delta[c] = brow[c] - run;
+            delta[c] = base_of(c) - run;
             run += cnt;
         }
     }
