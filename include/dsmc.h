@@ -55,11 +55,13 @@ enum {
      * order, every operation in a fixed IEEE order with no FMA contraction:
      * reproduces the reference recipe bit for bit. */
     DSMC_FP64_DETERMINISTIC = 0,
-    /* FP32 positions and velocities, FP64 accumulators; collisions of a cell
-     * processed 64 candidates at a time by one wavefront (NTC in
-     * distribution: each candidate pair is drawn and accepted exactly as in
-     * the sequential scheme, only non-conflicting candidates may run
-     * together).  Deterministic run to run and independent of batching. */
+    /* FP32 positions and velocities, FP64 accumulators; the candidates of a
+     * cell run in parallel rounds (a group of 4..64 lanes per cell for cells
+     * of fewer than 256 particles, a 256-thread workgroup for fuller ones),
+     * NTC in distribution: each candidate pair is drawn and accepted exactly
+     * as in the sequential scheme, and a candidate runs only after every
+     * lower-numbered candidate that shares a particle with it.  Deterministic
+     * run to run and independent of batching and launch shape. */
     DSMC_FP32_FAST = 1,
     /* The DSMC_FP32_FAST scheme with FP64 state. */
     DSMC_FP64_FAST = 2
