@@ -83,6 +83,8 @@ def assert_profiles_agree(gpu, ref, quantities=QUANT):
     p3 = 2 * stats.t.sf(3.0, nu)
     bound = stats.binom.ppf(0.999, len(z), p3)
     n3 = int((np.abs(z) > 3).sum())
+    print(f"profiles: {len(z)} Welch tests, {n3} with |z| > 3 (bound {bound:.0f}), "
+          f"max |z| {np.abs(z).max():.2f}, median dof {nu:.0f}")
     assert n3 <= bound, f"{n3} cells with |z| > 3 (bound {bound}, {len(z)} tests)"
     assert np.abs(z).max() < 5.0, f"max |z| = {np.abs(z).max():.2f}"
     return z
@@ -114,6 +116,8 @@ def test_fp32_matches_oracle_kn01_profiles_and_mass_flow(D):
     qg, qo = Q.mean(), ref["mass_flow"].mean()
     se = math.sqrt(Q.var(ddof=1) / len(Q) + ref["mass_flow"].var(ddof=1) / len(ref["mass_flow"]))
     rel = abs(qg - qo) / qo
+    print(f"mass flow: GPU {qg:.6f}, oracle {qo:.6f}, difference {100 * rel:.3f}% "
+          f"(3 SE = {300 * se / qo:.3f}%)")
     assert abs(qg - qo) < 3 * se, (qg, qo, se)
     assert rel <= 0.005, f"mass flow differs by {100 * rel:.3f}% (3 SE = {300 * se / qo:.3f}%)"
 
