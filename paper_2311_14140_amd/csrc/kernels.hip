@@ -113,8 +113,8 @@ __global__ void k_init(const InstDesc* __restrict__ descs) {
 // it moves parallel to the plates).
 template <class R> __device__ __forceinline__ R time_to_wall(const InstDesc& d, R y, R vy) {
     const R H = (R)d.H;
-    if (vy > R(0)) return (H - y) / vy;
-    if (vy < R(0)) return (R(0) - y) / vy;
+    if (vy > R(0)) return Num<R>::div(H - y, vy);
+    if (vy < R(0)) return Num<R>::div(R(0) - y, vy);
     return (R)INFINITY;
 }
 
@@ -150,10 +150,8 @@ __device__ __forceinline__ int flight_from_wall(const InstDesc& d, uint32_t step
     for (;;) {
         y = top ? H : R(0);
         Stream st(d.key0, d.key1, step, slot, (uint32_t)h, kTagWall);
-        R ua, ub;
-        Num<R>::uni2(st.next(), ua, ub);
-        const R vn = Num<R>::sqrt(R(-2) * Num<R>::log(ua)) * sd;
-        normal_pair<R>(st, sd, vx, vz);
+        R vn;
+        wall_draws<R>(st, sd, vn, vx, vz);
         vy = top ? -vn : vn;
         ++h;
         const R tw = time_to_wall<R>(d, y, vy);
@@ -189,10 +187,8 @@ __device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32
         y = top ? H : R(0);
         t = t - tw;
         Stream st(d.key0, d.key1, step, slot, (uint32_t)h, kTagWall);
-        R ua, ub;
-        Num<R>::uni2(st.next(), ua, ub);
-        const R vn = Num<R>::sqrt(R(-2) * Num<R>::log(ua)) * sd;
-        normal_pair<R>(st, sd, vx, vz);
+        R vn;
+        wall_draws<R>(st, sd, vn, vx, vz);
         vy = top ? -vn : vn;
         ++h;
     }

@@ -85,8 +85,10 @@ __device__ __forceinline__ float u24(uint32_t x) {
 }
 
 // Precision-dependent pieces of the recipe.  The FP64 specialisation is the
-// exact recipe (53-bit uniforms, series log); the FP32 one uses 24-bit
-// uniforms and the device logf.
+// exact recipe (53-bit uniforms, series log, correctly rounded division and
+// square root); the FP32 one is the fast mode's: 24-bit uniforms and the
+// hardware's single-instruction reciprocal, square root and logarithm (each
+// within about one ulp).
 template <class R> struct Num;
 
 template <> struct Num<double> {
@@ -96,6 +98,7 @@ template <> struct Num<double> {
     }
     __device__ __forceinline__ static double log(double u) { return series_log(u); }
     __device__ __forceinline__ static double sqrt(double v) { return __builtin_sqrt(v); }
+    __device__ __forceinline__ static double div(double a, double b) { return a / b; }
 };
 
 template <> struct Num<float> {
@@ -103,8 +106,14 @@ template <> struct Num<float> {
         a = u24(x.x);
         b = u24(x.z);
     }
-    __device__ __forceinline__ static float log(float u) { return __builtin_logf(u); }
-    __device__ __forceinline__ static float sqrt(float v) { return __builtin_sqrtf(v); }
+    // v_log_f32 is the base-2 logarithm
+    __device__ __forceinline__ static float log(float u) {
+        return __builtin_amdgcn_logf(u) * 0.693147180559945309f;
+    }
+    __device__ __forceinline__ static float sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+    __device__ __forceinline__ static float div(float a, float b) {
+        return a * __builtin_amdgcn_rcpf(b);
+    }
 };
 
 // Marsaglia-Bray polar method: a pair of independent normals with standard
@@ -119,7 +128,7 @@ __device__ __forceinline__ void normal_pair(Stream& st, R sd, R& n0, R& n1) {
         const R b = R(2) * ub - R(1);
         const R q = a * a + b * b;
         if (q > R(0) && q < R(1)) {
-            const R f = Num<R>::sqrt((R(-2) * Num<R>::log(q)) / q);
+            const R f = Num<R>::sqrt(Num<R>::div(R(-2) * Num<R>::log(q), q));
             n0 = (a * f) * sd;
             n1 = (b * f) * sd;
             return;
@@ -127,8 +136,59 @@ __device__ __forceinline__ void normal_pair(Stream& st, R sd, R& n0, R& n1) {
     }
 }
 
+// One polar-method attempt on two FP32 uniforms; true when accepted.
+__device__ __forceinline__ bool polar_try(uint32_t wa, uint32_t wb, float sd, float& n0, float& n1) {
+    const float a = 2.0f * u24(wa) - 1.0f, b = 2.0f * u24(wb) - 1.0f;
+    const float q = a * a + b * b;
+    if (!(q > 0.0f && q < 1.0f)) return false;
+    const float f = Num<float>::sqrt(Num<float>::div(-2.0f * Num<float>::log(q), q));
+    n0 = (a * f) * sd;
+    n1 = (b * f) * sd;
+    return true;
+}
+
+// The fast mode uses all four words of a call: two polar attempts per call.
+template <>
+__device__ __forceinline__ void normal_pair<float>(Stream& st, float sd, float& n0, float& n1) {
+    for (;;) {
+        const uint4 x = st.next();
+        if (polar_try(x.x, x.y, sd, n0, n1) || polar_try(x.z, x.w, sd, n0, n1)) return;
+    }
+}
+
+// The draws of one re-emission from a plate at T = sd^2: the normal speed
+// sqrt(-2 T ln U) and a tangential pair.  FP64: call 0 gives U, the pair
+// follows from later calls (the recipe's order).  FP32: call 0 gives U (word 0)
+// and the first polar attempt (words 1 and 2).
+template <class R>
+__device__ __forceinline__ void wall_draws(Stream& st, R sd, R& vn, R& t0, R& t1) {
+    R ua, ub;
+    Num<R>::uni2(st.next(), ua, ub);
+    vn = Num<R>::sqrt(R(-2) * Num<R>::log(ua)) * sd;
+    normal_pair<R>(st, sd, t0, t1);
+}
+
+template <>
+__device__ __forceinline__ void wall_draws<float>(Stream& st, float sd, float& vn, float& t0, float& t1) {
+    const uint4 x = st.next();
+    vn = Num<float>::sqrt(-2.0f * Num<float>::log(u24(x.x))) * sd;
+    if (!polar_try(x.y, x.z, sd, t0, t1)) normal_pair<float>(st, sd, t0, t1);
+}
+
 // Marsaglia (1972): uniform point on the unit sphere from a point uniform in
-// the unit disc: (2a sqrt(1-q), 2b sqrt(1-q), 1 - 2q).
+// the unit disc: (2a sqrt(1-q), 2b sqrt(1-q), 1 - 2q).  The FP32 version
+// makes two attempts per call (words 0-1, then 2-3).
+__device__ __forceinline__ bool sphere_try(uint32_t wa, uint32_t wb, float& dx, float& dy, float& dz) {
+    const float a = 2.0f * u24(wa) - 1.0f, b = 2.0f * u24(wb) - 1.0f;
+    const float q = a * a + b * b;
+    if (!(q < 1.0f)) return false;
+    const float r = 2.0f * Num<float>::sqrt(1.0f - q);
+    dx = a * r;
+    dy = b * r;
+    dz = 1.0f - 2.0f * q;
+    return true;
+}
+
 template <class R>
 __device__ __forceinline__ void sphere_point(Stream& st, R& dx, R& dy, R& dz) {
 #pragma clang fp contract(off)
@@ -145,6 +205,14 @@ __device__ __forceinline__ void sphere_point(Stream& st, R& dx, R& dy, R& dz) {
             dz = R(1) - R(2) * q;
             return;
         }
+    }
+}
+
+template <>
+__device__ __forceinline__ void sphere_point<float>(Stream& st, float& dx, float& dy, float& dz) {
+    for (;;) {
+        const uint4 x = st.next();
+        if (sphere_try(x.x, x.y, dx, dy, dz) || sphere_try(x.z, x.w, dx, dy, dz)) return;
     }
 }
 
