@@ -923,35 +923,65 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
 // The fast modes draw the same kind of NTC candidates as the sequential
 // scheme (pair and acceptance uniform per candidate from the cell's
 // counter-based stream) and run them either
-//   - groups of G lanes per cell (k_collide_group, G = 4..32 fixed per
-//     instance) for instances whose collision cells hold fewer than kCoopMin
-//     particles on average, or
-//   - a whole workgroup per cell (k_collide_fast), on velocities staged in
-//     LDS, in parallel rounds of blockDim candidates.  A candidate that shares
-//     a particle with a lower-numbered pending candidate waits for a later
-//     round (claims by atomicMin in an LDS table), so every executed
-//     candidate sees exactly the velocities of some sequential order: NTC in
-//     distribution.  Its acceptance test uses max(crmax at cell start, its
-//     own c_r); crmax is raised at the end of the cell.
-// The choice depends only on the instance's particles per collision cell, so
-// results depend only on the instance's data and streams, not on the group,
+//   - in groups of G lanes per cell (k_collide_bucket, G = 4..64) for
+//     instances whose collision cells hold fewer than kCoopMin particles on
+//     average, or
+//   - with a whole workgroup per cell (k_collide_fast), in parallel rounds of
+//     blockDim candidates,
+// on velocities staged in LDS.  Candidates are numbered in draw order; one
+// that shares a particle with a lower-numbered pending candidate waits for a
+// later round (claims by atomicMin in an LDS table), so the candidates that
+// touch a particle run in number order, as in the sequential scheme: NTC in
+// distribution.  The acceptance test uses max(crmax at cell start, its own
+// c_r); crmax is raised at the end of the cell.  Which path a cell takes, G
+// and the round a candidate runs in do not change any particle's result, so
+// states depend only on the instance's data and streams, not on the group,
 // the launch shape or the workgroup a cell lands in.
+// One pending candidate of a lane: its number, pair, acceptance uniform and
+// (FP32) the post-collision direction drawn with it.
+template <class R> struct Pend {
+    int64_t k;
+    int i, j;
+    R acc;
+    R dirz, dirp;  // FP32: cos(theta) in (-1, 1] and phi / 2pi in [0, 1)
+};
+
 template <class R> struct Cand;
 template <> struct Cand<float> {
-    __device__ __forceinline__ static void draw(Stream& st, float& a, float& b, float& c) {
+    // One call per candidate: words 0-2 give the pair and the acceptance
+    // uniform (top 24 bits each), word 3 gives cos(theta) and the three low
+    // bytes of words 0-2 give the azimuth.
+    __device__ __forceinline__ static void draw(Stream& st, float& a, float& b, Pend<float>& p) {
         const uint4 x = st.next();
         a = u24(x.x);
         b = u24(x.y);
-        c = u24(x.z);
+        p.acc = u24(x.z);
+        p.dirz = 2.0f * u24(x.w) - 1.0f;
+        p.dirp = (float)((x.x & 0xFFu) | ((x.y & 0xFFu) << 8) | ((x.z & 0xFFu) << 16)) * 0x1p-24f;
+    }
+    // Uniform direction on the sphere (Archimedes): z uniform, phi uniform;
+    // v_sin_f32 / v_cos_f32 take the angle in turns.
+    __device__ __forceinline__ static void direction(Stream&, const Pend<float>& p, float& dx,
+                                                     float& dy, float& dz) {
+        const float z = p.dirz;
+        const float omz = 1.0f - z * z;
+        const float r = Num<float>::sqrt(omz > 0.0f ? omz : 0.0f);
+        dx = r * __builtin_amdgcn_cosf(p.dirp);
+        dy = r * __builtin_amdgcn_sinf(p.dirp);
+        dz = z;
     }
 };
 template <> struct Cand<double> {
-    __device__ __forceinline__ static void draw(Stream& st, double& a, double& b, double& c) {
+    __device__ __forceinline__ static void draw(Stream& st, double& a, double& b, Pend<double>& p) {
         const uint4 x = st.next();
         a = u53(x.x, x.y);
         b = u53(x.z, x.w);
         const uint4 y = st.next();
-        c = u53(y.x, y.y);
+        p.acc = u53(y.x, y.y);
+    }
+    __device__ __forceinline__ static void direction(Stream& st, const Pend<double>&, double& dx,
+                                                     double& dy, double& dz) {
+        sphere_point<double>(st, dx, dy, dz);
     }
 };
 
@@ -961,19 +991,12 @@ __device__ __forceinline__ double wave_sum_fixed(double v) {
     return v;
 }
 
-// One pending candidate of a lane.
-template <class R> struct Pend {
-    int64_t k;
-    int i, j;
-    R acc;
-};
-
 template <class R>
 __device__ __forceinline__ void draw_candidate(const InstDesc& d, uint32_t s, int c, int nc,
                                                int64_t k, Pend<R>& p, Stream& st) {
     st = Stream(d.key0, d.key1, s, (uint32_t)c, (uint32_t)k, kTagColl);
     R ua, ub;
-    Cand<R>::draw(st, ua, ub, p.acc);
+    Cand<R>::draw(st, ua, ub, p);
     p.k = k;
     p.i = min((int)(ua * (R)nc), nc - 1);
     p.j = min((int)(ub * (R)(nc - 1)), nc - 2);
@@ -993,7 +1016,7 @@ __device__ __forceinline__ void run_candidate(Pend<R>& p, Stream& st, R crmr, V 
     const R cm = cr > crmr ? cr : crmr;
     if (p.acc * cm < cr) {
         R dx, dy, dz;
-        sphere_point<R>(st, dx, dy, dz);
+        Cand<R>::direction(st, p, dx, dy, dz);
         const R cmx = R(0.5) * (xi + xj), cmy = R(0.5) * (yi + yj), cmz = R(0.5) * (zi + zj);
         const R hh = R(0.5) * cr;
         vx[i] = cmx + hh * dx;
