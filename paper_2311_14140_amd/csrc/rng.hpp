@@ -176,19 +176,7 @@ __device__ __forceinline__ void wall_draws<float>(Stream& st, float sd, float& v
 }
 
 // Marsaglia (1972): uniform point on the unit sphere from a point uniform in
-// the unit disc: (2a sqrt(1-q), 2b sqrt(1-q), 1 - 2q).  The FP32 version
-// makes two attempts per call (words 0-1, then 2-3).
-__device__ __forceinline__ bool sphere_try(uint32_t wa, uint32_t wb, float& dx, float& dy, float& dz) {
-    const float a = 2.0f * u24(wa) - 1.0f, b = 2.0f * u24(wb) - 1.0f;
-    const float q = a * a + b * b;
-    if (!(q < 1.0f)) return false;
-    const float r = 2.0f * Num<float>::sqrt(1.0f - q);
-    dx = a * r;
-    dy = b * r;
-    dz = 1.0f - 2.0f * q;
-    return true;
-}
-
+// the unit disc: (2a sqrt(1-q), 2b sqrt(1-q), 1 - 2q).
 template <class R>
 __device__ __forceinline__ void sphere_point(Stream& st, R& dx, R& dy, R& dz) {
 #pragma clang fp contract(off)
@@ -205,14 +193,6 @@ __device__ __forceinline__ void sphere_point(Stream& st, R& dx, R& dy, R& dz) {
             dz = R(1) - R(2) * q;
             return;
         }
-    }
-}
-
-template <>
-__device__ __forceinline__ void sphere_point<float>(Stream& st, float& dx, float& dy, float& dz) {
-    for (;;) {
-        const uint4 x = st.next();
-        if (sphere_try(x.x, x.y, dx, dy, dz) || sphere_try(x.z, x.w, dx, dy, dz)) return;
     }
 }
 
