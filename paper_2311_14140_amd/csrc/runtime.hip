@@ -58,8 +58,9 @@ struct Plan {
         off_rem, off_acc, off_ncoll, off_est, off_sc, off_desc, total;
 };
 
-// Slots of a particle tile the scatter can lay out in LDS before writing.
-int stage_slots(size_t rb) { return rb == 4 ? 2048 : 1024; }
+// Slots of a particle tile the scatter can lay out in LDS before writing: the
+// tile the move-scatter holds in registers (256 x 6 in FP32, 256 x 4 in FP64).
+int stage_slots(size_t rb) { return kParticleThreads * (rb == 4 ? kScatterRegs32 : kScatterRegs64); }
 
 int base_items_per_thread(int32_t N, int32_t Cc, size_t rb) {
     // Tiles of 256 * k slots with at least 4 slots per collision cell keep
