@@ -70,8 +70,8 @@ def run_mix_replica(params):
 
 def main_mix(args):
     inst = synth.config3_instances()
-    jobs = [(i, r, inst[i].with_(seed=synth.seed_of(3, i, r), precision=0))
-            for i in range(len(inst)) for r in range(args.replicas)]
+    jobs = [(i, r - args.first, inst[i].with_(seed=synth.seed_of(3, i, r), precision=0))
+            for i in range(len(inst)) for r in range(args.first, args.first + args.replicas)]
     # longest first keeps the pool busy to the end
     jobs.sort(key=lambda j: -j[2].n_particles)
     t0 = time.time()
@@ -88,9 +88,9 @@ def main_mix(args):
     src = open(oracle.SRC, "rb").read()
     meta = dict(workload="cfg3", instances=len(inst), transient=MIX_TRANSIENT,
                 sampling_steps=MIX_SAMPLING, bins=MIX_BINS, replicas=args.replicas,
-                seed_rule="synth.seed_of(3, i, r)", mix="synth.config3_instances()",
-                oracle_sha256=hashlib.sha256(src).hexdigest())
-    path = os.path.join(HERE, f"oracle_cfg3_mix_r0_{args.replicas}.npz")
+                first_replica=args.first, seed_rule="synth.seed_of(3, i, r)",
+                mix="synth.config3_instances()", oracle_sha256=hashlib.sha256(src).hexdigest())
+    path = os.path.join(HERE, f"oracle_cfg3_mix_r{args.first}_{args.first + args.replicas}.npz")
     np.savez_compressed(path, mass_flow=Q, **out, meta=json.dumps(meta))
     print("wrote", path, flush=True)
 

@@ -73,20 +73,26 @@ def welch(a, b):
 
 
 def assert_profiles_agree(gpu, ref, quantities=QUANT):
+    """The agreement rule: the number of |z| > 3 within the 99.9% binomial
+    bound for the Student-t tail probability at the comparison's degrees of
+    freedom, and no |z| above the familywise 0.1% quantile of that Student-t
+    over all the tests (5 for many replicas; larger when few replicas give
+    heavy-tailed z)."""
     zs, nus = [], []
     for q in quantities:
         z, nu, _ = welch(gpu[q], ref[q])
-        zs.append(z)
-        nus.append(nu)
+        zs.append(np.ravel(z))
+        nus.append(np.ravel(nu))
     z = np.concatenate(zs)
     nu = float(np.median(np.concatenate(nus)))
     p3 = 2 * stats.t.sf(3.0, nu)
     bound = stats.binom.ppf(0.999, len(z), p3)
     n3 = int((np.abs(z) > 3).sum())
+    z_cap = max(5.0, float(stats.t.isf(0.001 / (2 * len(z)), nu)))
     print(f"profiles: {len(z)} Welch tests, {n3} with |z| > 3 (bound {bound:.0f}), "
-          f"max |z| {np.abs(z).max():.2f}, median dof {nu:.0f}")
+          f"max |z| {np.abs(z).max():.2f} (cap {z_cap:.2f}), median dof {nu:.0f}")
     assert n3 <= bound, f"{n3} cells with |z| > 3 (bound {bound}, {len(z)} tests)"
-    assert np.abs(z).max() < 5.0, f"max |z| = {np.abs(z).max():.2f}"
+    assert np.abs(z).max() < z_cap, f"max |z| = {np.abs(z).max():.2f} (cap {z_cap:.2f})"
     return z
 
 
@@ -134,15 +140,21 @@ def test_fp32_batched_mix_every_instance_matches_oracle(D):
     the oracle's replicas of the same instance on the same short schedule.
     Profiles are compared as 16 cell-bin averages per instance; the mass flow
     of each instance by its own Welch statistic."""
-    name = "oracle_cfg3_mix_r0_8.npz"
-    path = os.path.join(HERE, "golden", name)
-    if not os.path.exists(path):
+    files = sorted(f for f in os.listdir(os.path.join(HERE, "golden"))
+                   if f.startswith("oracle_cfg3_mix_r") and f.endswith(".npz"))
+    if not files:
         pytest.skip("oracle reference for the batched mix not generated")
-    d = np.load(path)
-    meta = json.loads(str(d["meta"]))
+    parts = [np.load(os.path.join(HERE, "golden", f)) for f in files]
+    metas = [json.loads(str(p["meta"])) for p in parts]
     inst = synth.config3_instances()
-    assert meta["instances"] == len(inst)
-    R, B = meta["replicas"], meta["bins"]
+    meta = metas[0]
+    for m in metas:
+        assert m["instances"] == len(inst)
+        assert (m["bins"], m["transient"], m["sampling_steps"]) == (
+            meta["bins"], meta["transient"], meta["sampling_steps"])
+    # replicas of all files along axis 1
+    d = {q: np.concatenate([p[q] for p in parts], axis=1) for q in QUANT + ("mass_flow",)}
+    R, B = d["ux"].shape[1], meta["bins"]
     T, S = meta["transient"], meta["sampling_steps"]
     gpu = {q: np.zeros((len(inst), R, B)) for q in QUANT}
     Q = np.zeros((len(inst), R))
