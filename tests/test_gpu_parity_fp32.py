@@ -409,3 +409,25 @@ def test_wall_reemission_paths_agree(D, prec_name):
         assert np.array_equal(np.asarray(x), np.asarray(z))
     assert np.isfinite(ra).all()
     assert np.array_equal(ra, rb)
+
+
+@pytest.mark.parametrize("prec_name", ["DSMC_FP32_FAST", "DSMC_FP64_DETERMINISTIC"])
+def test_non_finite_velocity_is_reported(D, prec_name):
+    """A non-finite velocity planted through set_state is carried through the
+    step without any out-of-range access (its cell index clamps to a valid
+    cell) and is reported as DSMC_ERR_NUMERIC at the next synchronising call."""
+    p = Params(kn=0.5, body_force=0.01, n_cells=50, particles_per_cell=40, seed=5,
+               n_transient=0, precision=getattr(D, prec_name))
+    with D.Solver(p) as s:
+        y, vx, vy, vz, _, _ = s.get_state()
+        y, vx, vy = np.array(y), np.array(vx), np.array(vy)
+        # mid-channel and moving parallel to the plates: no wall re-emission
+        # can replace the planted value
+        k = 25 * 40 + 7
+        y[k], vy[k], vx[k] = 0.5, 0.0, np.nan
+        s.set_state(y, vx, vy, vz, step=0)
+        s.step(2)
+        with pytest.raises(D.DsmcError) as err:
+            s.sample()
+        assert err.value.code == D.DSMC_ERR_NUMERIC
+        assert "non-finite" in str(err.value), str(err.value)
