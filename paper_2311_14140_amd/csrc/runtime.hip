@@ -223,6 +223,21 @@ struct dsmc_handle {
     std::string err;
 };
 
+// A lane of a group: a subset of its members with their own work lists, step
+// graph and stream.  The lanes of a group run concurrently; each step forks
+// from the group's stream and joins back to it.
+struct Lane {
+    std::vector<dsmc_handle*> members;
+    void* d_mem = nullptr;   // device-side work lists
+    size_t d_bytes = 0;
+    Work work{};
+    hipGraphExec_t gexec = nullptr;  // graph of kGraphSteps steps
+    hipGraph_t graph = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipStream_t stream = nullptr;    // own stream when the group has several lanes
+    hipEvent_t done = nullptr;
+};
+
 struct dsmc_group {
     hipStream_t stream = nullptr;
     int mode = -1;
@@ -231,15 +246,10 @@ struct dsmc_group {
     bool dirty = true;
     int tile_mult = 0;   // 0 = automatic
     int ppb = 0;         // target particles per fast-collide workgroup, 0 = automatic
-    // device-side work lists
-    void* d_mem = nullptr;
-    size_t d_bytes = 0;
-    Work work{};
     unsigned phase = DSMC_PHASE_ALL;
-    // graph of kGraphSteps steps
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    hipStream_t cap_stream = nullptr;
+    int n_lanes = 1;     // lanes in use (lanes.size() may be larger)
+    std::vector<Lane> lanes;
+    hipEvent_t fork = nullptr;
     std::string err;
 };
 
@@ -251,11 +261,26 @@ hipStream_t stream_of(const dsmc_handle* h) {
     return h->group ? h->group->stream : h->stream;
 }
 
-void drop_graph(dsmc_group* g) {
-    if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
-    if (g->graph) (void)hipGraphDestroy(g->graph);
-    g->gexec = nullptr;
-    g->graph = nullptr;
+void drop_graph(Lane& l) {
+    if (l.gexec) (void)hipGraphExecDestroy(l.gexec);
+    if (l.graph) (void)hipGraphDestroy(l.graph);
+    l.gexec = nullptr;
+    l.graph = nullptr;
+}
+
+void drop_graphs(dsmc_group* g) {
+    for (Lane& l : g->lanes) drop_graph(l);
+}
+
+// Groups of at least this many particles (and two or more members) run in
+// two lanes: the kernels are latency-bound, so a second lane fills the gaps
+// and tails of the first (about 10% on the 256-instance mix).
+constexpr int64_t kLaneMinParticles = 2000000;
+constexpr int kMaxLanes = 2;
+
+// The stream the lane's steps go to.
+hipStream_t lane_stream(const dsmc_group* g, const Lane& l) {
+    return g->n_lanes > 1 ? l.stream : g->stream;
 }
 
 int auto_cpb(const dsmc_handle* h, int target_particles) {
@@ -320,16 +345,16 @@ std::vector<T> xcd_stripes(const std::vector<T>& in) {
 }
 
 // (Re)build the device work lists and launch shapes of a group.
-int rebuild(dsmc_group* g) {
-    drop_graph(g);
-    const int n = (int)g->members.size();
+// Work lists and launch shapes of one lane.
+int build_lane(dsmc_group* g, Lane& lane) {
+    const int n = (int)lane.members.size();
     std::vector<InstDesc> descs(n);
     std::vector<int2> tiles;
     std::vector<int4> cols, cblocks, gblocks;
     int max_cc = 1;
     int cap = 64, group_cap = 64;
     for (int i = 0; i < n; ++i) {
-        dsmc_handle* h = g->members[i];
+        dsmc_handle* h = lane.members[i];
         InstDesc d = h->desc;
         if (!g->solo) d.phase_mask = DSMC_PHASE_ALL;
         const double per_cell = (double)d.N / (double)d.Cc;
@@ -409,16 +434,14 @@ int rebuild(dsmc_group* g) {
     const size_t need = bytes_of(n, sizeof(InstDesc)) + bytes_of(tiles.size(), sizeof(int2)) +
                         bytes_of(cols.size(), sizeof(int4)) + bytes_of(cblocks.size(), sizeof(int4)) +
                         bytes_of(gblocks.size(), sizeof(int4));
-    // the stream may still be using the previous lists
-    HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
-    if (need > g->d_bytes) {
-        if (g->d_mem) (void)hipFree(g->d_mem);
-        g->d_mem = nullptr;
-        g->d_bytes = 0;
-        HIP_TRY(&g->err, hipMalloc(&g->d_mem, need));
-        g->d_bytes = need;
+    if (need > lane.d_bytes) {
+        if (lane.d_mem) (void)hipFree(lane.d_mem);
+        lane.d_mem = nullptr;
+        lane.d_bytes = 0;
+        HIP_TRY(&g->err, hipMalloc(&lane.d_mem, need));
+        lane.d_bytes = need;
     }
-    char* base = (char*)g->d_mem;
+    char* base = (char*)lane.d_mem;
     size_t o = 0;
     InstDesc* d_desc = (InstDesc*)(base + o);
     o += bytes_of(n, sizeof(InstDesc));
@@ -434,21 +457,60 @@ int rebuild(dsmc_group* g) {
     if (!cols.empty()) HIP_TRY(&g->err, hipMemcpy(d_cols, cols.data(), sizeof(int4) * cols.size(), hipMemcpyHostToDevice));
     if (!cblocks.empty()) HIP_TRY(&g->err, hipMemcpy(d_cb, cblocks.data(), sizeof(int4) * cblocks.size(), hipMemcpyHostToDevice));
     if (!gblocks.empty()) HIP_TRY(&g->err, hipMemcpy(d_lb, gblocks.data(), sizeof(int4) * gblocks.size(), hipMemcpyHostToDevice));
-    g->work.desc = d_desc;
-    g->work.n_inst = n;
-    g->work.tiles = d_tiles;
-    g->work.n_tiles = (int)tiles.size();
-    g->work.cols = d_cols;
-    g->work.n_cols = (int)cols.size();
-    g->work.cblocks = d_cb;
-    g->work.n_cblocks = (int)cblocks.size();
-    g->work.gblocks = d_lb;
-    g->work.n_gblocks = (int)gblocks.size();
-    g->work.group_cap = group_cap;
-    g->work.max_cc = max_cc;
-    g->work.stage_max = stage_max;
-    g->work.fast_cap = cap;
-    g->phase = (g->solo && n == 1 && g->members[0]->p.debug_phase_mask)
+    Work& w = lane.work;
+    w.desc = d_desc;
+    w.n_inst = n;
+    w.tiles = d_tiles;
+    w.n_tiles = (int)tiles.size();
+    w.cols = d_cols;
+    w.n_cols = (int)cols.size();
+    w.cblocks = d_cb;
+    w.n_cblocks = (int)cblocks.size();
+    w.gblocks = d_lb;
+    w.n_gblocks = (int)gblocks.size();
+    w.group_cap = group_cap;
+    w.max_cc = max_cc;
+    w.stage_max = stage_max;
+    w.fast_cap = cap;
+    return DSMC_OK;
+}
+
+// (Re)build the lanes of a group: members are dealt to the lanes largest
+// first, each to the lane with the fewest particles so far.
+int rebuild(dsmc_group* g) {
+    drop_graphs(g);
+    // the streams may still be using the previous lists
+    HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
+    for (Lane& l : g->lanes)
+        if (l.stream) HIP_TRY(&g->err, hipStreamSynchronize(l.stream));
+    int64_t total = 0;
+    for (const dsmc_handle* h : g->members) total += h->plan.N;
+    const int nl = (!g->solo && g->members.size() >= 2 && total >= kLaneMinParticles) ? kMaxLanes : 1;
+    if ((int)g->lanes.size() < nl) g->lanes.resize(nl);
+    g->n_lanes = nl;
+    if (nl > 1 && !g->fork) HIP_TRY(&g->err, hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
+    for (int k = 0; k < nl; ++k) {
+        Lane& l = g->lanes[k];
+        l.members.clear();
+        if (nl > 1) {
+            if (!l.stream) HIP_TRY(&g->err, hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking));
+            if (!l.done) HIP_TRY(&g->err, hipEventCreateWithFlags(&l.done, hipEventDisableTiming));
+        }
+    }
+    std::vector<dsmc_handle*> order(g->members);
+    std::stable_sort(order.begin(), order.end(),
+                     [](const dsmc_handle* a, const dsmc_handle* b) { return a->plan.N > b->plan.N; });
+    std::vector<int64_t> load(nl, 0);
+    for (dsmc_handle* h : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        g->lanes[k].members.push_back(h);
+        load[k] += h->plan.N;
+    }
+    for (int k = 0; k < nl; ++k) {
+        const int r = build_lane(g, g->lanes[k]);
+        if (r) return r;
+    }
+    g->phase = (g->solo && g->members.size() == 1 && g->members[0]->p.debug_phase_mask)
                    ? g->members[0]->p.debug_phase_mask
                    : (unsigned)DSMC_PHASE_ALL;
     g->dirty = false;
@@ -463,23 +525,34 @@ int enqueue_steps(dsmc_group* g, int64_t n_steps) {
         if (r) return r;
     }
     const Mode mode = (Mode)g->mode;
-    int64_t left = n_steps;
-    if (left >= kGraphSteps && g->phase == DSMC_PHASE_ALL) {
-        if (!g->gexec) {
-            if (!g->cap_stream) HIP_TRY(&g->err, hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-            HIP_TRY(&g->err, hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-            for (int k = 0; k < kGraphSteps; ++k) launch_step(g->work, mode, g->phase, g->cap_stream);
-            hipGraph_t graph = nullptr;
-            HIP_TRY(&g->err, hipStreamEndCapture(g->cap_stream, &graph));
-            g->graph = graph;
-            HIP_TRY(&g->err, hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0));
+    const int nl = g->n_lanes;
+    if (nl > 1) HIP_TRY(&g->err, hipEventRecord(g->fork, g->stream));
+    for (int li = 0; li < nl; ++li) {
+        Lane& l = g->lanes[li];
+        const hipStream_t st = lane_stream(g, l);
+        if (nl > 1) HIP_TRY(&g->err, hipStreamWaitEvent(st, g->fork, 0));
+        int64_t left = n_steps;
+        if (left >= kGraphSteps && g->phase == DSMC_PHASE_ALL) {
+            if (!l.gexec) {
+                if (!l.cap_stream) HIP_TRY(&g->err, hipStreamCreateWithFlags(&l.cap_stream, hipStreamNonBlocking));
+                HIP_TRY(&g->err, hipStreamBeginCapture(l.cap_stream, hipStreamCaptureModeThreadLocal));
+                for (int k = 0; k < kGraphSteps; ++k) launch_step(l.work, mode, g->phase, l.cap_stream);
+                hipGraph_t graph = nullptr;
+                HIP_TRY(&g->err, hipStreamEndCapture(l.cap_stream, &graph));
+                l.graph = graph;
+                HIP_TRY(&g->err, hipGraphInstantiate(&l.gexec, graph, nullptr, nullptr, 0));
+            }
+            while (left >= kGraphSteps) {
+                HIP_TRY(&g->err, hipGraphLaunch(l.gexec, st));
+                left -= kGraphSteps;
+            }
         }
-        while (left >= kGraphSteps) {
-            HIP_TRY(&g->err, hipGraphLaunch(g->gexec, g->stream));
-            left -= kGraphSteps;
+        for (int64_t k = 0; k < left; ++k) launch_step(l.work, mode, g->phase, st);
+        if (nl > 1) {
+            HIP_TRY(&g->err, hipEventRecord(l.done, st));
+            HIP_TRY(&g->err, hipStreamWaitEvent(g->stream, l.done, 0));
         }
     }
-    for (int64_t k = 0; k < left; ++k) launch_step(g->work, mode, g->phase, g->stream);
     HIP_TRY(&g->err, hipGetLastError());
     return DSMC_OK;
 }
@@ -503,9 +576,15 @@ int group_init(dsmc_group* g, hipStream_t stream, bool solo) {
 void group_free(dsmc_group* g) {
     if (!g) return;
     if (g->stream || !g->members.empty()) (void)hipStreamSynchronize(g->stream);
-    drop_graph(g);
-    if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
-    if (g->d_mem) (void)hipFree(g->d_mem);
+    for (Lane& l : g->lanes) {
+        if (l.stream) (void)hipStreamSynchronize(l.stream);
+        drop_graph(l);
+        if (l.cap_stream) (void)hipStreamDestroy(l.cap_stream);
+        if (l.stream) (void)hipStreamDestroy(l.stream);
+        if (l.done) (void)hipEventDestroy(l.done);
+        if (l.d_mem) (void)hipFree(l.d_mem);
+    }
+    if (g->fork) (void)hipEventDestroy(g->fork);
     delete g;
 }
 
@@ -837,24 +916,31 @@ int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
     }
     // all steps are enqueued before any wait, so the device runs them back to
     // back and the events bracket kernel execution, not host launch gaps
-    std::vector<hipEvent_t> ev((size_t)n_steps * 7, nullptr);
+    // the lanes of a group are timed one after another on the group's
+    // stream, so each kernel's time is its own (summed over the lanes)
+    const int nl = g->n_lanes;
+    const size_t nblk = (size_t)n_steps * nl;
+    std::vector<hipEvent_t> ev(nblk * 7, nullptr);
     int rc = DSMC_OK;
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) rc = fail(&h->err, DSMC_ERR_DEVICE, "hipEventCreate failed");
     double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (rc == DSMC_OK && nl > 1) (void)hipStreamSynchronize(g->stream);
     const auto t0 = std::chrono::steady_clock::now();
     if (rc == DSMC_OK) {
         for (int64_t k = 0; k < n_steps; ++k)
-            launch_step_timed(g->work, (Mode)g->mode, g->phase, g->stream, ev.data() + 7 * k);
+            for (int li = 0; li < nl; ++li)
+                launch_step_timed(g->lanes[li].work, (Mode)g->mode, g->phase, g->stream,
+                                  ev.data() + 7 * ((size_t)k * nl + li));
         if (hipEventSynchronize(ev.back()) != hipSuccess)
             rc = fail(&h->err, DSMC_ERR_DEVICE, "event synchronise failed");
     }
     const auto t1 = std::chrono::steady_clock::now();
     if (rc == DSMC_OK) {
-        for (int64_t k = 0; k < n_steps; ++k)
+        for (size_t b = 0; b < nblk; ++b)
             for (int i = 0; i < 6; ++i) {
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, ev[7 * k + i], ev[7 * k + i + 1]) == hipSuccess) acc[i] += ms;
+                if (hipEventElapsedTime(&ms, ev[7 * b + i], ev[7 * b + i + 1]) == hipSuccess) acc[i] += ms;
             }
     }
     for (auto e : ev)

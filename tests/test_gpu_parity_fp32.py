@@ -431,3 +431,34 @@ def test_non_finite_velocity_is_reported(D, prec_name):
             s.sample()
         assert err.value.code == D.DSMC_ERR_NUMERIC
         assert "non-finite" in str(err.value), str(err.value)
+
+
+def test_two_lane_group_equals_alone(D):
+    """A group of more than 2e6 particles runs its members in two concurrent
+    lanes (own streams, work lists and graphs); every instance must still be
+    bit-identical to the same instance stepped alone."""
+    ps = [Params(kn=0.3, body_force=0.01, n_cells=600, particles_per_cell=2500, seed=31,
+                 n_transient=3, precision=D.DSMC_FP32_FAST),
+          Params(kn=2.0, body_force=0.005, n_cells=800, particles_per_cell=100, seed=32,
+                 n_transient=3, precision=D.DSMC_FP32_FAST),
+          Params(kn=0.08, body_force=0.02, n_cells=400, particles_per_cell=1500, seed=33,
+                 n_transient=3, precision=D.DSMC_FP32_FAST)]
+    assert sum(p.n_particles for p in ps) > 2_000_000
+    alone = []
+    for p in ps:
+        with D.Solver(p) as s:
+            s.step(11)
+            alone.append((s.get_state(), s.sample(raw=True)["raw"]))
+    g = D.Group()
+    sols = [D.Solver(p) for p in ps]
+    for s in sols:
+        g.add(s)
+    g.step(11)   # one 8-step graph per lane, then 3 direct steps
+    g.sync()
+    for s, (st, raw) in zip(sols, alone):
+        for a, b in zip(s.get_state(), st):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        assert np.array_equal(s.sample(raw=True)["raw"], raw)
+    g.close()
+    for s in sols:
+        s.close()
