@@ -20,7 +20,7 @@ constexpr int kCoopTable = kFastWaves * kClaimTable;  // its claim table (the wa
 constexpr int kMaxCellsPerKey = 128;   // cells of one sort bucket (a power of two up to this)
 // records per lane the move-scatter holds in registers (FP32, FP64): tiles of
 // bucket-sorted instances are 256 times this many slots
-constexpr int kScatterRegs32 = 6, kScatterRegs64 = 4;
+constexpr int kScatterRegs32 = 5, kScatterRegs64 = 4;
 
 // Scalars an instance keeps on the device so that a step is the same launch
 // sequence every time (and can be replayed from a graph).
