@@ -112,6 +112,10 @@ class Subject:
         # profiling a member of a group profiles the group's steps
         return self.sols[0].profile(n)
 
+    def lanes(self):
+        # each kernel of a step is launched once per lane of the group
+        return self.group.lanes() if self.group else 1
+
     def sample(self):
         return [s.sample(reset=True) for s in self.sols]
 
@@ -271,8 +275,12 @@ def main():
     kern = {k: prof[k] / args.profile_steps for k in dsmc.Solver.PHASES}
     dom = max(kern, key=kern.get)
     bucketed = rb == 4 and all(p.particles_per_cell / p.n_sub < 256 for p in plist)
-    dom_bytes = kernel_bytes(dom, N, Cc, rb, coll_frac, True, bucketed)
-    achieved = dom_bytes / (kern[dom] * 1e-3) / 1e9
+    # per launch: a step launches each kernel once per lane, on that lane's
+    # share of the particles (the profiler's dispatches are these launches)
+    lanes = sub.lanes()
+    dom_bytes = kernel_bytes(dom, N, Cc, rb, coll_frac, True, bucketed) / lanes
+    dom_ms = kern[dom] / lanes
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     step_bytes = sum(kernel_bytes(k, N, Cc, rb, coll_frac, True, bucketed) for k in kern)
     log("per-kernel ms/step: " + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()))
     sub.close()
@@ -350,8 +358,8 @@ def main():
                    "collision_cells": Cc, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload, dom), "kernel_ms": kern[dom],
-                     "algorithmic_bytes_per_launch": dom_bytes},
+                     "traffic": measured_traffic(args.workload, dom), "kernel_ms": dom_ms,
+                     "algorithmic_bytes_per_launch": dom_bytes, "launches_per_step": lanes},
         "step_roofline": {"algorithmic_bytes_per_step": step_bytes,
                           "achieved_GBps": step_bytes / (el / args.steps) / 1e9,
                           "frac": step_bytes / (el / args.steps) / 1e9 / HBM_PEAK_GBS},

@@ -196,6 +196,12 @@ int dsmc_group_remove(dsmc_group *g, dsmc_handle *h);
 int dsmc_group_step(dsmc_group *g, int64_t n_steps);
 int dsmc_group_sync(dsmc_group *g);
 int dsmc_group_size(const dsmc_group *g, int32_t *n_members);
+/* Lanes the members were split into at the last step: a group of at least
+ * 2e6 particles and two or more members runs in two lanes (each with its own
+ * stream, work lists and step graph, forked from and joined back to the
+ * group's stream), so each of a step's kernels is launched once per lane.
+ * Results do not depend on it. */
+int dsmc_group_lanes(const dsmc_group *g, int32_t *n_lanes);
 int dsmc_group_destroy(dsmc_group *g);
 
 /* Launch-shape tuning of a group: tile_mult multiplies each member's base

@@ -1015,6 +1015,12 @@ int dsmc_group_size(const dsmc_group* g, int32_t* n) {
     return DSMC_OK;
 }
 
+int dsmc_group_lanes(const dsmc_group* g, int32_t* n) {
+    if (!g || !n) return fail(nullptr, DSMC_ERR_INVALID_ARG, "NULL argument");
+    *n = (int32_t)g->n_lanes;
+    return DSMC_OK;
+}
+
 int dsmc_group_destroy(dsmc_group* g) {
     if (!g) return DSMC_OK;
     if (g->stream || !g->members.empty()) (void)hipStreamSynchronize(g->stream);

@@ -35,7 +35,7 @@ EXPORTS = (
     "dsmc_sync", "dsmc_destroy", "dsmc_get_state", "dsmc_set_state", "dsmc_get_cells",
     "dsmc_set_cells", "dsmc_info", "dsmc_status_string", "dsmc_last_error",
     "dsmc_group_create", "dsmc_group_add", "dsmc_group_remove", "dsmc_group_step",
-    "dsmc_group_sync", "dsmc_group_size", "dsmc_group_destroy", "dsmc_group_set_tuning",
+    "dsmc_group_sync", "dsmc_group_size", "dsmc_group_lanes", "dsmc_group_destroy", "dsmc_group_set_tuning",
     "dsmc_group_autotune", "dsmc_profile_step",
 )
 
@@ -91,6 +91,7 @@ def _load():
         "dsmc_group_step": [vp, i64],
         "dsmc_group_sync": [vp],
         "dsmc_group_size": [vp, ct.POINTER(i32)],
+        "dsmc_group_lanes": [vp, ct.POINTER(i32)],
         "dsmc_group_destroy": [vp],
         "dsmc_group_set_tuning": [vp, i32, i32],
         "dsmc_group_autotune": [vp, ct.POINTER(i32), ct.POINTER(i32)],
@@ -311,6 +312,13 @@ class Group:
 
     def sync(self):
         _check(lib.dsmc_group_sync(self._g))
+
+    def lanes(self) -> int:
+        """Lanes the members ran in at the last step (each kernel of a step is
+        launched once per lane)."""
+        n = ct.c_int32()
+        _check(lib.dsmc_group_lanes(self._g, ct.byref(n)))
+        return n.value
 
     def set_tuning(self, tile_mult: int = 0, particles_per_block: int = 0):
         _check(lib.dsmc_group_set_tuning(self._g, int(tile_mult), int(particles_per_block)))
