@@ -140,7 +140,7 @@ def time_single(dsmc, torch, p, steps, label):
     """particle-steps/s of one instance (sampling steps, graph-replayed)."""
     p = p.with_(n_transient=4)
     with dsmc.Solver(p) as s:
-        s.step(8)
+        s.step(10)  # past the capture of the instance's step graph
         el = _timed(torch, s.step, s.sync, steps)
         prof = s.profile(4)
         return {"value": s.N * steps / el, "unit": "particle-steps/s", "particles": s.N,
@@ -157,7 +157,7 @@ def fp64_plain(dsmc, torch, params_list, steps):
     ps_total, el_total = 0, 0.0
     for p in params_list:
         with dsmc.Solver(p.with_(n_transient=0, precision=FP64_DETERMINISTIC)) as d:
-            d.step(2)
+            d.step(10)  # past the capture of the instance's step graph
             el_total += _timed(torch, d.step, d.sync, steps)
             ps_total += d.N * steps
     return {"value": ps_total / el_total, "unit": "particle-steps/s", "steps": steps,
