@@ -119,6 +119,30 @@ def serving_trace(n_requests: int = 2000, rate_hz: float = 200.0, seed: int = 4,
     return out
 
 
+# The surrogate-training runs (Sec. 3): cells of 0.005 (200 across the gap),
+# 50 particles per cell, one training sample per 100 steps, 100 samples per
+# training step, 1000 training steps.
+TRAINING_CELLS = 200
+TRAINING_PPC = 50
+STEPS_PER_SAMPLE = 100
+SAMPLES_PER_TRAINING_STEP = 100
+TRAINING_STEPS = 1000
+
+
+def training_force(kn: float, mach: float = 0.05) -> float:
+    """Body force F giving a centre-line Mach number near ``mach`` (Sec. 3):
+    the no-slip Stokes centre speed sqrt(pi) F / (8 Kn) plus a slip speed of
+    about F, with the speed of sound sqrt(5/6) v0 of a monatomic gas."""
+    return mach * math.sqrt(5.0 / 6.0) / (math.sqrt(math.pi) / (8.0 * kn) + 1.0)
+
+
+def training_case(kn: float, replica: int = 0, precision: int = FP32_FAST) -> Params:
+    """One surrogate-training run at ``kn`` (seeds of workload 5)."""
+    return Params(kn=kn, body_force=training_force(kn), n_cells=TRAINING_CELLS,
+                  particles_per_cell=TRAINING_PPC, n_transient=transient_steps(kn),
+                  seed=seed_of(5, int(round(1000 * kn)), replica), precision=precision)
+
+
 WORKLOADS = {
     "cfg0": (CONFIG0, CONFIG0_STEPS),
     "cfg1": (CONFIG1, CONFIG1_STEPS),
