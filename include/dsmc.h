@@ -101,12 +101,21 @@ typedef struct dsmc_moments {
     double *n;                  /* density over the mean density */
     double *ux, *uy, *uz;       /* mean velocity over v0 */
     double *T;                  /* temperature over T_ref */
-    double *pxy;                /* shear stress P_xy over P0 */
+    double *pxy;                /* shear stress P_xy over P0, sampled after the collisions */
     double *qx, *qy;            /* heat flux over P0 v0 */
-    double *raw_sums;           /* optional: n_cells*n_sub*12 FP64 sums per collision cell:
-                                   1, vx, vy, vz, vx2, vy2, vz2, vxvy, vxvz, vyvz, v2vx, v2vy */
+    double *raw_sums;           /* optional: n_cells*n_sub*13 FP64 sums per collision cell:
+                                   1, vx, vy, vz, vx2, vy2, vz2, vxvy, vxvz, vyvz, v2vx, v2vy
+                                   after the collisions, then vxvy before them */
     double mass_flow;           /* out: integral of n u_x dy over (n_mean H v0); NaN if K = 0 */
     int64_t n_collisions;       /* out: accepted collisions in the window */
+    double *pxy_mid;            /* time-centred shear stress over P0: the mean of the
+                                   kinetic estimates before and after the collisions.
+                                   Collisions relax the stress by about dt / tau_p per step,
+                                   so the post-collision value sits that fraction below the
+                                   momentum flux of the free flights; the mean of the two
+                                   is the flux to second order in dt and satisfies the
+                                   momentum balance dP/dy = 2F (Eqs. 1 and 6).  This is
+                                   the P^DSMC of the constitutive surrogates (Eq. 13). */
 } dsmc_moments;
 
 typedef struct dsmc_handle dsmc_handle;

@@ -22,7 +22,7 @@ LIB = os.path.join(_HERE, "libdsmc_oracle.so")
 PHASE_MOVE, PHASE_SORT, PHASE_COLLIDE, PHASE_SAMPLE = 1, 2, 4, 8
 PHASE_ALL = 15
 TAG_INIT, TAG_WALL, TAG_COLL = 1, 2, 3
-NMOM = 12
+NMOM = 13
 
 _lock = threading.Lock()
 _lib = None
@@ -64,7 +64,7 @@ def lib():
             L.or_destroy.argtypes = [vp]
             L.or_step.argtypes = [vp, ct.c_int64, ct.c_uint32]
             L.or_reset_window.argtypes = [vp]
-            L.or_estimators.argtypes = [vp] + [vp] * 9
+            L.or_estimators.argtypes = [vp] + [vp] * 10
             L.or_n_particles.restype = ct.c_int32
             L.or_n_particles.argtypes = [vp]
             L.or_n_coll_cells.restype = ct.c_int32
@@ -237,11 +237,11 @@ class Oracle:
 
     def estimators(self) -> dict:
         C = self.C
-        arrs = {k: np.zeros(C) for k in ("n", "ux", "uy", "uz", "T", "pxy", "qx", "qy")}
+        arrs = {k: np.zeros(C) for k in ("n", "ux", "uy", "uz", "T", "pxy", "qx", "qy", "pxy_mid")}
         Q = np.zeros(1)
         self._L.or_estimators(self._h, *[_ptr(arrs[k]) for k in
                                          ("n", "ux", "uy", "uz", "T", "pxy", "qx", "qy")],
-                              _ptr(Q))
+                              _ptr(Q), _ptr(arrs["pxy_mid"]))
         arrs["mass_flow"] = float(Q[0])
         arrs["n_sampled_steps"] = self.n_sampled
         return arrs

@@ -34,8 +34,15 @@
  *     normal pairs by the Marsaglia-Bray polar method; isotropic directions by
  *     Marsaglia's (1972) sphere-point method.  No trigonometric function.
  *   - Sampling accumulates twelve FP64 sums per cell every step after the
- *     transient; estimators give density, velocity, temperature, shear stress
- *     (the P_xy of Eqs. 1-2 and 11-13), heat flux and the mass flow rate.
+ *     transient, after the collide phase, and the sum of vx vy before it;
+ *     estimators give density, velocity, temperature, shear stress, heat flux
+ *     and the mass flow rate.  The shear stress P^DSMC of Eq. 13 is taken as
+ *     the time-centred estimate, the mean of the kinetic stresses before and
+ *     after the collisions: collisions relax the stress by about dt / tau_p per
+ *     step, so the value after them is that fraction below the momentum flux
+ *     carried by the free flights, while the mean is that flux to second order
+ *     in dt (it satisfies the momentum balance of Eqs. 1 and 6).  The
+ *     post-collision stress is reported as well.
  *
  * Build: cc -O2 -ffp-contract=off -fPIC -shared (no fast-math).  Every
  * floating-point expression below is written in the order it is evaluated.
@@ -55,7 +62,8 @@
 #define PHASE_SAMPLE 8u
 #define PHASE_ALL 15u
 
-#define NMOM 12 /* 1, vx, vy, vz, vx2, vy2, vz2, vxvy, vxvz, vyvz, v2vx, v2vy */
+#define NMOM 13 /* 1, vx, vy, vz, vx2, vy2, vz2, vxvy, vxvz, vyvz, v2vx, v2vy after the
+                   collisions; vxvy before them */
 
 typedef struct or_params {
     double kn;
@@ -529,8 +537,8 @@ static void phase_collide(or_state *S, int64_t step)
 }
 
 /* -------------------------------------------------------------- sample */
-/* Per collision cell, the step's twelve sums over its slots in slot order,
- * then added to the window's accumulators. */
+/* Per collision cell, the step's twelve sums over its slots in slot order
+ * after the collide phase, then added to the window's accumulators. */
 static void phase_sample(or_state *S)
 {
     for (int32_t c = 0; c < S->Cc; ++c) {
@@ -558,6 +566,19 @@ static void phase_sample(or_state *S)
     }
 }
 
+/* Per collision cell, the sum of vx vy over its slots in slot order before the
+ * collide phase: the stress a sampling step sees before the collisions relax
+ * it, for the time-centred stress estimate. */
+static void phase_sample_pre(or_state *S)
+{
+    for (int32_t c = 0; c < S->Cc; ++c) {
+        double s = 0.0;
+        int32_t o = S->offset[c], n = S->count[c];
+        for (int32_t q = o; q < o + n; ++q) s += S->vx[q] * S->vy[q];
+        S->acc[(size_t)c * NMOM + 12] += s;
+    }
+}
+
 /* ----------------------------------------------------------------- step */
 void or_step(or_state *S, int64_t n_steps, uint32_t phase_mask)
 {
@@ -566,8 +587,10 @@ void or_step(or_state *S, int64_t n_steps, uint32_t phase_mask)
         int64_t step = S->step + 1;
         if (phase_mask & PHASE_MOVE) phase_move(S, step);
         if (phase_mask & PHASE_SORT) phase_sort(S);
+        const int sampling = (phase_mask & PHASE_SAMPLE) && step > S->p.n_transient;
+        if (sampling) phase_sample_pre(S);
         if (phase_mask & PHASE_COLLIDE) phase_collide(S, step);
-        if ((phase_mask & PHASE_SAMPLE) && step > S->p.n_transient) {
+        if (sampling) {
             phase_sample(S);
             S->n_sampled += 1;
         }
@@ -588,13 +611,17 @@ void or_reset_window(or_state *S)
  *   nu = S0 C / (K N)                     density over the mean density
  *   u_a = S1_a / S0, M_ab = S2_ab/S0 - u_a u_b, T = trace(M)/3
  *   P_xy = nu M_xy                        shear stress over n kT_ref
+ *   P_xy,mid = nu ((S_xy + S_xy,pre)/2 / S0 - u_x u_y)
+ *                                         the time-centred stress: the mean of
+ *                                         the kinetic estimates before and
+ *                                         after the collide phase
  *   <|c|^2 c_a> from the raw moments, q_a = nu <|c|^2 c_a> / 2
  *   Q = sum_c S1_x / (K N)                mass flow over n H
  * Velocities, heat flux and mass flow are returned over v0 = sqrt(2) and the
  * stress over P0, the normalisation of Eq. 6.  Outputs are NaN when K = 0 or
  * a cell saw no particle. */
 void or_estimators(const or_state *S, double *nu, double *ux, double *uy, double *uz,
-                   double *T, double *pxy, double *qx, double *qy, double *Q)
+                   double *T, double *pxy, double *qx, double *qy, double *Q, double *pxy_mid)
 {
     const double v0 = sqrt(2.0);
     const int32_t C = S->C, ns = S->p.n_sub;
@@ -626,6 +653,7 @@ void or_estimators(const or_state *S, double *nu, double *ux, double *uy, double
         if (uz) uz[c] = w / v0;
         if (T) T[c] = ((mxx + myy) + mzz) / 3.0;
         if (pxy) pxy[c] = n_c * mxy;
+        if (pxy_mid) pxy_mid[c] = n_c * ((0.5 * (s[7] + s[12])) / s[0] - u * v);
         if (qx) qx[c] = (0.5 * n_c * cx) / v0;
         if (qy) qy[c] = (0.5 * n_c * cy) / v0;
     }

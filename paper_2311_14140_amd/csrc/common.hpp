@@ -5,8 +5,12 @@
 
 namespace dsmc {
 
-constexpr int kMoments = 12;       // 1, vx, vy, vz, vx2, vy2, vz2, vxvy, vxvz, vyvz, v2vx, v2vy
-constexpr int kEstPerCell = 8;     // n, ux, uy, uz, T, pxy, qx, qy
+// Per-cell sums of a step: 1, vx, vy, vz, vx2, vy2, vz2, vxvy, vxvz, vyvz,
+// v2vx, v2vy after the collisions, and vxvy before them (the only one of the
+// stress's sums that the collisions change).
+constexpr int kMoments = 13;
+constexpr int kMomPreXY = 12;      // index of the pre-collision vxvy sum
+constexpr int kEstPerCell = 9;     // n, ux, uy, uz, T, pxy, qx, qy, pxy_mid
 constexpr int kParticleThreads = 256;  // threads per particle tile (move, scatter)
 constexpr int kScatterWaves = kParticleThreads / 64;  // wavefronts of a scatter tile
 constexpr int kColThreads = 256;       // cells per workgroup of the column-scan kernels

@@ -852,7 +852,8 @@ __device__ __forceinline__ void mom_add(Mom& m, double x, double y, double z) {
 // accepted with probability c_r / crmax (hard spheres) and then scatters
 // isotropically about the centre of mass.  Candidates run in order, so the
 // result is the reference recipe's to the last bit.  The sampling step's
-// twelve FP64 sums of the cell follow in slot order.
+// FP64 sums of the cell follow in slot order: vxvy before the collisions, the
+// twelve moments after them.
 __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__ descs,
                                                    const int4* __restrict__ work, int do_collide) {
     const int4 w = work[blockIdx.x];
@@ -867,6 +868,10 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
         const gptr<double> vx = b.vx + o;
         const gptr<double> vy = b.vy + o;
         const gptr<double> vz = b.vz + o;
+        // the stress sum before the collisions, in slot order
+        double pre = 0.0;
+        if (sample)
+            for (int q = 0; q < n; ++q) pre += vx[q] * vy[q];
         if (do_collide && n >= 2) {
             double crm = d.crmax[c];
             const double mreal = (((0.5 * (double)n) * (double)(n - 1)) * crm) * d.kntc + d.rem[c];
@@ -912,6 +917,7 @@ __global__ __launch_bounds__(64) void k_collide_det(const InstDesc* __restrict__
             Mom m;
             mom_zero(m);
             for (int q = 0; q < n; ++q) mom_add(m, vx[q], vy[q], vz[q]);
+            m.s[kMomPreXY] = pre;
             double* a = d.acc + c;  // moment k of cell c at k * Cc + c
 #pragma unroll
             for (int k = 0; k < kMoments; ++k) a[(size_t)k * d.Cc] += m.s[k];
@@ -1121,11 +1127,12 @@ __device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, V 
 // partials added in wavefront order).
 template <class R, class V>
 __device__ __forceinline__ void cell_moments(V vx, V vy, V vz, int o, int nc, int first,
-                                             int stride, double tot[kMoments]) {
+                                             int stride, double pre, double tot[kMoments]) {
     Mom m;
     mom_zero(m);
     for (int q = first; q < nc; q += stride)
         mom_add(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
+    m.s[kMomPreXY] = pre;
 #pragma unroll
     for (int k = 0; k < kMoments; ++k) tot[k] = wave_sum_fixed(m.s[k]);
 }
@@ -1142,10 +1149,18 @@ __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int
     for (int c = c0; c < c1; ++c) {
         const int nc = d.count[c];
         const int o = d.offset[c] - s0;
+        // this thread's share of the stress sum before the collisions; the
+        // barrier keeps every read ahead of the first collision's writes
+        double pre = 0.0;
+        if (sample) {
+            for (int q = (int)threadIdx.x; q < nc; q += (int)blockDim.x)
+                pre += (double)vx[o + q] * (double)vy[o + q];
+            __syncthreads();
+        }
         if (do_collide && nc >= 2) coop_ntc<R, V>(d, s, c, nc, o, vx, vy, vz, claims, sh);
         if (sample) {
             double tot[kMoments];
-            cell_moments<R, V>(vx, vy, vz, o, nc, (int)threadIdx.x, (int)blockDim.x, tot);
+            cell_moments<R, V>(vx, vy, vz, o, nc, (int)threadIdx.x, (int)blockDim.x, pre, tot);
             if (lane == 0)
                 for (int k = 0; k < kMoments; ++k) sh.mom[wv][k] = tot[k];
             __syncthreads();
@@ -1245,6 +1260,12 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
                 M = (int64_t)mf;
             }
         }
+        // this lane's share of the cell's stress sum before the collisions
+        // (the group's lanes run in lockstep and each loaded value is added
+        // before the first candidate runs, so no collision write precedes it)
+        double pre = 0.0;
+        if (has && sample)
+            for (int q = lane - grp * G; q < nc; q += G) pre += (double)vx[o + q] * (double)vy[o + q];
         const R crmr = (R)crm0;
         R lane_max = R(0);
         uint32_t lane_coll = 0;
@@ -1290,6 +1311,7 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
         if (has && sample)
             for (int q = lane - grp * G; q < nc; q += G)
                 mom_add(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
+        m.s[kMomPreXY] = pre;
         for (int off = G >> 1; off >= 1; off >>= 1) {
             const double other = __shfl_xor(mx, off, 64);
             mx = other > mx ? other : mx;
@@ -1552,8 +1574,9 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
 // ----------------------------------------------------------- estimators
 // Per sampling cell (its collision cells summed in order) with K sampled
 // steps and N particles: density nu = S0 C/(K N); u = S1/S0;
-// M_ab = S2_ab/S0 - u_a u_b; T = trace(M)/3; P_xy = nu M_xy;
-// <|c|^2 c_a> from the raw moments; q_a = nu <|c|^2 c_a>/2; mass flow
+// M_ab = S2_ab/S0 - u_a u_b; T = trace(M)/3; P_xy = nu M_xy; the
+// time-centred P_xy from the mean of the vxvy sums before and after the
+// collisions; <|c|^2 c_a> from the raw moments; q_a = nu <|c|^2 c_a>/2; mass flow
 // Q = sum S1_x/(K N).  Velocities, heat fluxes and Q are divided by
 // v0 = sqrt(2) and stresses are over n kT: the dimensionless variables of
 // Eq. 6.  The sum of Q runs in cell order: all threads stage the cells'
@@ -1598,6 +1621,7 @@ __global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ d
             e[5 * C + c] = n_c * mxy;
             e[6 * C + c] = (0.5 * n_c * cx) / v0;
             e[7 * C + c] = (0.5 * n_c * cy) / v0;
+            e[8 * C + c] = n_c * ((0.5 * (s[7] + s[kMomPreXY])) / s[0] - u * v);
         }
         __syncthreads();
         if (threadIdx.x == 0)

@@ -761,11 +761,12 @@ int dsmc_sample(dsmc_handle* h, dsmc_moments* out, int reset_window) {
     HIP_TRY(&h->err, hipMemcpyAsync(&sc, h->desc.sc, sizeof sc, hipMemcpyDeviceToHost, s));
     int r = sync_check(h);
     if (r) return r;
-    double* dst[kEstPerCell] = {out->n, out->ux, out->uy, out->uz, out->T, out->pxy, out->qx, out->qy};
+    double* dst[kEstPerCell] = {out->n,  out->ux, out->uy, out->uz,     out->T,
+                                out->pxy, out->qx, out->qy, out->pxy_mid};
     for (int m = 0; m < kEstPerCell; ++m)
         if (dst[m]) std::memcpy(dst[m], est.data() + (size_t)m * C, sizeof(double) * C);
     if (out->raw_sums) {
-        // device layout is moment-major; the ABI's is 12 sums per collision cell
+        // device layout is moment-major; the ABI's is 13 sums per collision cell
         const size_t cc = (size_t)h->plan.Cc;
         for (size_t c = 0; c < cc; ++c)
             for (int k = 0; k < kMoments; ++k) out->raw_sums[c * kMoments + k] = raw[(size_t)k * cc + c];

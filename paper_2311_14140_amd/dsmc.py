@@ -28,7 +28,7 @@ DSMC_FP64_FAST = 2
 
 DSMC_PHASE_MOVE, DSMC_PHASE_SORT, DSMC_PHASE_COLLIDE, DSMC_PHASE_SAMPLE = 1, 2, 4, 8
 DSMC_PHASE_ALL = 15
-N_MOMENTS = 12
+N_MOMENTS = 13
 
 EXPORTS = (
     "dsmc_params_init", "dsmc_footprint_bytes", "dsmc_create", "dsmc_step", "dsmc_sample",
@@ -62,7 +62,7 @@ class dsmc_moments(ct.Structure):
     _fields_ = [("n_cells", ct.c_int32), ("pad_", ct.c_int32), ("n_sampled_steps", ct.c_int64),
                 ("n", _dp), ("ux", _dp), ("uy", _dp), ("uz", _dp), ("T", _dp), ("pxy", _dp),
                 ("qx", _dp), ("qy", _dp), ("raw_sums", _dp), ("mass_flow", ct.c_double),
-                ("n_collisions", ct.c_int64)]
+                ("n_collisions", ct.c_int64), ("pxy_mid", _dp)]
 
 
 def _load():
@@ -217,7 +217,7 @@ class Solver:
 
     def sample(self, reset: bool = False, raw: bool = False) -> dict:
         C = self.C
-        arrs = {k: np.zeros(C) for k in ("n", "ux", "uy", "uz", "T", "pxy", "qx", "qy")}
+        arrs = {k: np.zeros(C) for k in ("n", "ux", "uy", "uz", "T", "pxy", "qx", "qy", "pxy_mid")}
         m = dsmc_moments()
         m.n_cells = C
         for k, a in arrs.items():

@@ -252,7 +252,11 @@ class SurrogateTrainer:
 def collect_windows(solvers, n_windows: int, steps_per_sample: int = 100, group=None,
                     on_window=None):
     """Run ``n_windows`` sampling windows of ``steps_per_sample`` steps on the
-    GPU and hand each solver's window to ``on_window(k, ux, pxy)``.
+    GPU and hand each solver's window to ``on_window(k, ux, pxy)``, the
+    stress being the time-centred estimate (the mean of the kinetic stresses
+    before and after the collisions, which keeps the momentum balance; the
+    value after the collisions alone lies a first-order amount in dt below
+    the momentum flux).
 
     ``solvers`` are ``dsmc.Solver`` objects past their transient; with
     ``group`` (a ``dsmc.Group`` holding them all) one group step advances them
@@ -270,7 +274,7 @@ def collect_windows(solvers, n_windows: int, steps_per_sample: int = 100, group=
                 raise RuntimeError(f"window of {w['n_sampled_steps']} sampled steps, "
                                    f"expected {steps_per_sample} (transient not over?)")
             if on_window is not None:
-                on_window(k, w["ux"], w["pxy"])
+                on_window(k, w["ux"], w["pxy_mid"])
     return time.perf_counter() - t0
 
 

@@ -143,6 +143,18 @@ def training_case(kn: float, replica: int = 0, precision: int = FP32_FAST) -> Pa
                   seed=seed_of(5, int(round(1000 * kn)), replica), precision=precision)
 
 
+# The benchmark DSMC of Sec. 3: the training flow with 500 particles per cell,
+# sampled 10^6 steps after the transient.
+BENCHMARK_PPC = 500
+BENCHMARK_STEPS = 10 ** 6
+
+
+def benchmark_case(kn: float, replica: int = 0, precision: int = FP32_FAST) -> Params:
+    """One benchmark run at ``kn`` (seeds of workload 6)."""
+    return training_case(kn, precision=precision).with_(
+        particles_per_cell=BENCHMARK_PPC, seed=seed_of(6, int(round(1000 * kn)), replica))
+
+
 WORKLOADS = {
     "cfg0": (CONFIG0, CONFIG0_STEPS),
     "cfg1": (CONFIG1, CONFIG1_STEPS),

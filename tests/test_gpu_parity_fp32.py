@@ -462,3 +462,51 @@ def test_two_lane_group_equals_alone(D):
     g.close()
     for s in sols:
         s.close()
+
+
+@pytest.mark.parametrize("prec_name", ["DSMC_FP32_FAST", "DSMC_FP64_FAST"])
+@pytest.mark.parametrize("ppc", [30, 400])
+def test_pre_collision_sum_without_collisions_equals_post(D, prec_name, ppc):
+    """With the collide phase off (the production move, sort and sampling
+    kernels, collisions skipped) the stress sum before the collisions is the
+    one after them, bit for bit, in both the small-cell group path (30 per
+    cell) and the whole-workgroup path (400 per cell)."""
+    prec = getattr(D, prec_name)
+    p = Params(kn=0.5, body_force=0.02, n_cells=60, particles_per_cell=ppc, seed=41,
+               n_transient=0, precision=prec)
+    mask = D.DSMC_PHASE_MOVE | D.DSMC_PHASE_SORT | D.DSMC_PHASE_SAMPLE
+    with D.Solver(p, debug_phase_mask=mask) as s:
+        s.step(25)
+        e = s.sample(raw=True)
+    raw = e["raw"]
+    assert e["n_sampled_steps"] == 25 and np.all(raw[:, 0] > 0)
+    assert np.array_equal(raw[:, 12], raw[:, 7])
+    assert np.array_equal(e["pxy_mid"], e["pxy"])
+
+
+def test_time_centred_stress_keeps_the_momentum_balance(D):
+    """The FP32 path's time-centred stress meets dP/dy = 2F in the interior
+    (Eqs. 1 and 6), while the stress sampled after the collisions lies about
+    dt / (2 tau_p) below it (0.089 at the default step), as in the oracle."""
+    F, C, R = 0.05, 40, 16
+    ps = [Params(kn=1.0, body_force=F, n_cells=C, particles_per_cell=100, n_transient=300,
+                 seed=synth.seed_of(7, 0, r), precision=D.DSMC_FP32_FAST) for r in range(R)]
+    sols = [D.Solver(p) for p in ps]
+    g = D.Group()
+    for s in sols:
+        g.add(s)
+    g.step(30300)
+    es = [s.sample() for s in sols]
+    g.close()
+    for s in sols:
+        s.close()
+    dt = 0.2 / math.sqrt(2.0)
+    tau_p = 1.016 * 0.625 * math.sqrt(math.pi) / math.sqrt(2.0)
+    y = (np.arange(C) + 0.5) / C
+    sl = slice(4, C - 4)
+    A = np.vstack([y[sl] - 0.5, np.ones(C - 8)]).T
+    for k, want in (("pxy", 1.0 - 0.5 * dt / tau_p), ("pxy_mid", 1.0)):
+        slopes = np.array([np.linalg.lstsq(A, e[k][sl], rcond=None)[0][0] / (2 * F) for e in es])
+        m, se = slopes.mean(), slopes.std(ddof=1) / math.sqrt(R)
+        print(f"{k}: slope/(2F) {m:.4f} +- {se:.4f} (expected {want:.4f})", flush=True)
+        assert abs(m - want) < 4 * se + 0.005
