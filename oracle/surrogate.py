@@ -12,8 +12,11 @@ reference, stated where it is used):
   - du/dy of the Newton-law error E (Eq. 13): second-order central
     differences in the interior cells and second-order one-sided
     differences in the first and last cells, on cell-centred values.
-  - The velocity "at the wall" of the slip models (Eqs. 11-12): the value in
-    the cell next to the wall.
+  - The velocity "at the wall" of the slip models (Eqs. 11-12), u(y_bot)
+    and u(y_top): the cell-centred profile extrapolated linearly to the
+    plate from the two cells next to it, u_w = (3 u_1 - u_2) / 2, half a
+    cell beyond the first centre.  (The value of the first cell itself,
+    half a cell from the plate, is kept as an option.)
   - The wall shear stress P^CFD of the slip model: for the force-driven
     channel the momentum balance fixes P_xy = 2F(y - 1/2) whatever the
     constitutive law, so P = -F at the bottom plate and +F at the top (the
@@ -92,15 +95,27 @@ def constitutive_system(us, Ps, kn, k, b=None):
     return np.array(rows, dtype=np.float64).reshape(len(t), k), np.array(t, dtype=np.float64)
 
 
-def slip_system(us, force, slip):
-    """Targets u_j(y_bot), u_j(y_top) (the cells next to the plates) and the
-    slip model's design column -P(y_bot) = F, P(y_top) = F (Eq. 12 and
-    Appendix A); the no-slip model (Eq. 11) has no column."""
+def wall_velocities(u, wall="extrapolated"):
+    """u(y_bot), u(y_top) of one cell-centred profile: extrapolated to the
+    plates from the two nearest cells, or the nearest cells' values."""
+    n = len(u)
+    if wall == "cell":
+        return u[0], u[n - 1]
+    if wall != "extrapolated":
+        raise ValueError(wall)
+    return 1.5 * u[0] - 0.5 * u[1], 1.5 * u[n - 1] - 0.5 * u[n - 2]
+
+
+def slip_system(us, force, slip, wall="extrapolated"):
+    """Targets u_j(y_bot), u_j(y_top) and the slip model's design column
+    -P(y_bot) = F, P(y_top) = F (Eq. 12 and Appendix A); the no-slip model
+    (Eq. 11) has no column."""
     t = []
     rows = []
     for u in us:
-        t.append(u[0])
-        t.append(u[len(u) - 1])
+        ub, ut = wall_velocities(u, wall)
+        t.append(ub)
+        t.append(ut)
         rows.append([force] if slip else [])
         rows.append([force] if slip else [])
     return np.array(rows, dtype=np.float64).reshape(len(t), 1 if slip else 0), np.array(t, dtype=np.float64)

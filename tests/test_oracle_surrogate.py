@@ -137,6 +137,19 @@ def test_selection_recovers_a_planted_stress_correction():
     assert np.all(np.abs(m - a) < 4 * Sd), (m, a, Sd)
 
 
+def test_wall_velocity_extrapolation_is_exact_for_linear_profiles():
+    """Half a cell beyond the first centre: exact for a profile linear near
+    each plate; the cell reading returns the end cells."""
+    n = 16
+    y = (np.arange(n) + 0.5) / n
+    u = np.where(y < 0.5, 0.2 + 3.0 * y, 0.2 + 3.0 * (1 - y))
+    ub, ut = S.wall_velocities(list(u))
+    assert math.isclose(ub, 0.2, abs_tol=1e-15) and math.isclose(ut, 0.2, abs_tol=1e-15)
+    assert S.wall_velocities(list(u), "cell") == (u[0], u[-1])
+    with pytest.raises(ValueError):
+        S.wall_velocities(list(u), "centre")
+
+
 def test_slip_model_recovers_the_slip_coefficient():
     """Wall velocities sigma F plus noise (Eq. 12 with P = -F, +F at the
     plates): the slip model wins and sigma is recovered."""
@@ -148,8 +161,11 @@ def test_slip_model_recovers_the_slip_coefficient():
         u[0] = sigma * F + rng.normal(scale=0.004)
         u[-1] = sigma * F + rng.normal(scale=0.004)
         us.append(u)
-    fits = [S.bayesian_ridge(*S.slip_system(us, F, slip)) for slip in (False, True)]
+    fits = [S.bayesian_ridge(*S.slip_system(us, F, slip, wall="cell")) for slip in (False, True)]
     p = S.model_probabilities([f["log_evidence"] for f in fits])
     assert p[1] > 0.999
     m, sd = fits[1]["m"][0], math.sqrt(fits[1]["S"][0, 0])
     assert abs(m - sigma) < 4 * sd
+    # the same plates seen through the extrapolated reading: u_w = 1.5 u_1
+    ext = S.bayesian_ridge(*S.slip_system(us, F, True))
+    assert abs(ext["m"][0] - 1.5 * sigma) < 4 * 1.5 * sd
