@@ -173,6 +173,9 @@ def main():
                    seconds_training_dsmc=r.run.seconds_dsmc, seconds_train=r.run.seconds_train,
                    seconds_macro=r.solution.seconds,
                    seconds_bench=r.benchmark.seconds if r.benchmark else None, **r.compare())
+        out["p_constitutive_history"] = [[round(float(v), 4) for v in h.p_constitutive]
+                                         for h in r.trainer.history]
+        out["p_slip_history"] = [round(float(h.p_boundary[1]), 6) for h in r.trainer.history]
         print(json.dumps(out), flush=True)
 
 

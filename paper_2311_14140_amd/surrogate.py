@@ -29,7 +29,9 @@ where every re-estimation is a few elementwise products.
 
 Points the paper leaves open are taken as follows: du/dy by second-order
 central differences inside and second-order one-sided differences in the two
-end cells; the wall velocity is the velocity of the cell next to the wall; the
+end cells; the wall velocity u(y_bot), u(y_top) of Eqs. 11-12 is the profile
+extrapolated linearly to the plate from its two nearest cells (the nearest
+cell's own value, half a cell away, is an option); the
 macro wall stress of the force-driven channel is -F at the bottom plate and +F
 at the top (the momentum balance in the units of Eq. 6 fixes P = 2F(y - 1/2)
 whatever the constitutive law); Table 1 is looked up at the tabulated Kn nearest
@@ -175,10 +177,15 @@ class SurrogateTrainer:
     ``kn`` and ``force`` are the Kn and F of Eq. 6 for the flow; ``n_cells``
     the cells of the profiles, of equal width across the gap.  ``cells`` (an
     index array or boolean mask) restricts the constitutive targets to a set
-    of cells, the gradient still being taken over the whole profile."""
+    of cells, the gradient still being taken over the whole profile.
+    ``wall`` picks the wall velocity of the boundary models:
+    ``"extrapolated"`` (to the plate) or ``"cell"`` (the nearest cell)."""
 
     def __init__(self, kn: float, force: float, n_cells: int, exponents=None,
-                 max_order: int = MAX_ORDER, cells=None):
+                 max_order: int = MAX_ORDER, cells=None, wall: str = "extrapolated"):
+        if wall not in ("extrapolated", "cell"):
+            raise ValueError("wall must be 'extrapolated' or 'cell'")
+        self.wall = wall
         if n_cells < 3:
             raise ValueError("the gradient needs at least three cells")
         if not 0 <= max_order <= MAX_ORDER:
@@ -226,7 +233,11 @@ class SurrogateTrainer:
         self._Esum += float(np.sum(E))
         p_bot, p_top = (-self.force, self.force) if wall_stress is None else wall_stress
         x_bot, x_top = -float(p_bot), float(p_top)
-        u_bot, u_top = ux[:, 0], ux[:, -1]
+        if self.wall == "cell":
+            u_bot, u_top = ux[:, 0], ux[:, -1]
+        else:
+            u_bot = 1.5 * ux[:, 0] - 0.5 * ux[:, 1]
+            u_top = 1.5 * ux[:, -1] - 0.5 * ux[:, -2]
         self._xx += S * (x_bot * x_bot + x_top * x_top)
         self._xu += x_bot * float(u_bot.sum()) + x_top * float(u_top.sum())
         self._uu += float(u_bot @ u_bot + u_top @ u_top)

@@ -27,10 +27,10 @@ def synthetic_windows(kn, force, n_cells, n_samples, seed, sigma=1.1, a=(-0.03, 
     return ux, pxy
 
 
-def oracle_step(ux, pxy, kn, force):
+def oracle_step(ux, pxy, kn, force, wall="extrapolated"):
     us, Ps = list(ux), list(pxy)
     cons = [ref.bayesian_ridge(*ref.constitutive_system(us, Ps, kn, k)) for k in range(4)]
-    bnd = [ref.bayesian_ridge(*ref.slip_system(us, force, s)) for s in (False, True)]
+    bnd = [ref.bayesian_ridge(*ref.slip_system(us, force, s, wall)) for s in (False, True)]
     return cons, bnd
 
 
@@ -44,16 +44,17 @@ def assert_posterior_equal(p, r, what):
     assert abs(p.log_evidence - r["log_evidence"]) < 1e-7 * max(1.0, abs(r["log_evidence"])), what
 
 
-@pytest.mark.parametrize("kn,force,n_cells,n_samples,seed", [
-    (0.1, 0.0142, 200, 100, 1), (1.0, 0.0374, 200, 100, 2), (0.5, 0.03, 64, 300, 3),
-    (0.05, 0.0084, 200, 40, 4)])
-def test_training_step_matches_oracle(kn, force, n_cells, n_samples, seed):
+@pytest.mark.parametrize("kn,force,n_cells,n_samples,seed,wall", [
+    (0.1, 0.0142, 200, 100, 1, "extrapolated"), (1.0, 0.0374, 200, 100, 2, "extrapolated"),
+    (0.5, 0.03, 64, 300, 3, "cell"), (0.05, 0.0084, 200, 40, 4, "extrapolated"),
+    (1.0, 0.0374, 200, 100, 2, "cell")])
+def test_training_step_matches_oracle(kn, force, n_cells, n_samples, seed, wall):
     ux, pxy = synthetic_windows(kn, force, n_cells, n_samples, seed)
-    t = sg.SurrogateTrainer(kn, force, n_cells)
+    t = sg.SurrogateTrainer(kn, force, n_cells, wall=wall)
     assert t.exponents == ref.exponents(kn)
     t.add(ux, pxy)
     step = t.train()
-    cons, bnd = oracle_step(ux, pxy, kn, force)
+    cons, bnd = oracle_step(ux, pxy, kn, force, wall)
     for k in range(4):
         assert_posterior_equal(step.constitutive[k], cons[k], f"C_{k}")
     assert_posterior_equal(step.boundary[0], bnd[0], "no-slip")
@@ -122,10 +123,15 @@ def test_selection_on_planted_models():
     t.add(ux, pxy)
     s = t.train()
     assert s.slip and s.p_boundary[1] > 1 - 1e-12
-    # the wall velocity is read in the first cell, half a cell from the plate
+    # extrapolated to the plate, the planted parabola's wall value is sigma F
+    assert abs(s.sigma_p - 1.1) < 4 * math.sqrt(s.boundary[1].S[0, 0])
+    # read in the first cell, half a cell from the plate, it is larger
+    c = sg.SurrogateTrainer(kn, F, 200, wall="cell")
+    c.add(ux, pxy)
     y0 = 0.5 / 200
     sigma_cell = 1.1 + y0 * (1 - y0) / (2 * kn / math.sqrt(math.pi))
-    assert abs(s.sigma_p - sigma_cell) < 4 * math.sqrt(s.boundary[1].S[0, 0])
+    sc = c.train()
+    assert abs(sc.sigma_p - sigma_cell) < 4 * math.sqrt(sc.boundary[1].S[0, 0])
     assert s.p_constitutive[0] < 1e-12 and s.p_constitutive[1] < 1e-6
     m2 = s.constitutive[2]
     sd = np.sqrt(np.diag(m2.S))
@@ -158,6 +164,8 @@ def test_rejects_bad_windows():
         sg.SurrogateTrainer(0.1, 0.01, 2)
     with pytest.raises(ValueError):
         sg.SurrogateTrainer(0.1, 0.01, 50, max_order=4)
+    with pytest.raises(ValueError):
+        sg.SurrogateTrainer(0.1, 0.01, 50, wall="plate")
 
 
 def test_table_lookup_matches_oracle():
