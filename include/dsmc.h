@@ -205,6 +205,22 @@ int dsmc_group_remove(dsmc_group *g, dsmc_handle *h);
 int dsmc_group_step(dsmc_group *g, int64_t n_steps);
 int dsmc_group_sync(dsmc_group *g);
 int dsmc_group_size(const dsmc_group *g, int32_t *n_members);
+/* The windows of every member at once: the estimators of dsmc_sample for
+ * member i (in the order the members were added, removals closing the gaps)
+ * into outs[i], n_outs = the member count, and with reset_window != 0 a new
+ * window for all of them.  One launch computes every member's estimators
+ * into a device staging buffer, one copy brings it to pinned host memory and
+ * one synchronisation of the group's stream ends the call, instead of a
+ * launch, copies and a synchronisation per member: the way to take the
+ * 100-step training samples of Sec. 3 from many instances.  Raw sums are
+ * not returned (raw_sums must be NULL; dsmc_sample gives them).  The staging
+ * buffers are allocated on the first call after the membership changes and
+ * kept with the group.  NUMERIC if a member flagged a non-finite velocity or
+ * a lost particle: that member's n_sampled_steps is set to -1, its arrays are
+ * left untouched, the others are filled, and the error message names the
+ * first such member.  INVALID_ARG for a wrong n_outs, a too-small n_cells or
+ * non-NULL raw_sums. */
+int dsmc_group_sample(dsmc_group *g, dsmc_moments *outs, int32_t n_outs, int reset_window);
 /* Lanes the members were split into at the last step: a group of at least
  * 2e6 particles and two or more members runs in two lanes (each with its own
  * stream, work lists and step graph, forked from and joined back to the

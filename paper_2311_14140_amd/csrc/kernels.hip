@@ -1581,11 +1581,13 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
 // v0 = sqrt(2) and stresses are over n kT: the dimensionless variables of
 // Eq. 6.  The sum of Q runs in cell order: all threads stage the cells'
 // x-momentum sums in LDS and one thread adds them in order.
-__global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ descs) {
-    constexpr int kChunk = 2048;  // sampling cells whose x-momentum sums are staged at a time
-    __shared__ double col[kChunk];
-    __shared__ unsigned long long coll_part[256];
-    const InstDesc& d = descs[blockIdx.x];
+constexpr int kFinalizeChunk = 2048;  // sampling cells whose x-momentum sums are staged at a time
+
+// The estimators of one instance into est (kEstPerCell * C + 3 doubles), by
+// the whole 256-thread workgroup; col and coll_part are its LDS.
+__device__ void finalize_into(const InstDesc& d, double* est, double* col,
+                              unsigned long long* coll_part) {
+    constexpr int kChunk = kFinalizeChunk;
     const int C = d.C, ns = d.n_sub;
     const double K = (double)d.sc->n_sampled, N = (double)d.N;
     const double v0 = __builtin_sqrt(2.0);
@@ -1612,7 +1614,7 @@ __global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ d
                                2.0 * (((u * s[4] + v * s[7]) + ww * s[8]) / s[0])) + 2.0 * u * usq;
             const double cy = ((s[11] / s[0] - v * (trace2 / s[0])) -
                                2.0 * (((u * s[7] + v * s[5]) + ww * s[9]) / s[0])) + 2.0 * v * usq;
-            double* e = d.est;
+            double* e = est;
             e[0 * C + c] = n_c;
             e[1 * C + c] = u / v0;
             e[2 * C + c] = v / v0;
@@ -1635,10 +1637,31 @@ __global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ d
     if (threadIdx.x == 0) {
         unsigned long long tot = 0;
         for (int t = 0; t < (int)blockDim.x; ++t) tot += coll_part[t];
-        d.est[kEstPerCell * C] = (q / (K * N)) / v0;
-        d.est[kEstPerCell * C + 1] = K;
-        d.est[kEstPerCell * C + 2] = (double)tot;
+        est[kEstPerCell * C] = (q / (K * N)) / v0;
+        est[kEstPerCell * C + 1] = K;
+        est[kEstPerCell * C + 2] = (double)tot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ descs) {
+    __shared__ double col[kFinalizeChunk];
+    __shared__ unsigned long long coll_part[256];
+    const InstDesc& d = descs[blockIdx.x];
+    finalize_into(d, d.est, col, coll_part);
+}
+
+// The estimators of many instances into one staging buffer: instance b's
+// block at stage + off[b] holds its kEstPerCell * C + 3 estimator values,
+// then its status word, so one copy brings a whole group's windows back.
+__global__ __launch_bounds__(256) void k_finalize_staged(const InstDesc* __restrict__ descs,
+                                                        const int64_t* __restrict__ off,
+                                                        double* __restrict__ stage) {
+    __shared__ double col[kFinalizeChunk];
+    __shared__ unsigned long long coll_part[256];
+    const InstDesc& d = descs[blockIdx.x];
+    double* est = stage + off[blockIdx.x];
+    finalize_into(d, est, col, coll_part);
+    if (threadIdx.x == 0) est[kEstPerCell * d.C + 3] = (double)d.sc->status;
 }
 
 __global__ __launch_bounds__(256) void k_reset_window(const InstDesc* __restrict__ descs) {
@@ -1796,6 +1819,11 @@ void launch_step_timed(const Work& w, Mode mode, unsigned phase, hipStream_t s, 
 
 void launch_finalize(const InstDesc* d_desc, int n_inst, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(256), 0, s, d_desc);
+}
+
+void launch_finalize_staged(const InstDesc* d_desc, const int64_t* d_off, double* d_stage,
+                            int n_inst, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_staged, dim3(n_inst), dim3(256), 0, s, d_desc, d_off, d_stage);
 }
 
 void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s) {

@@ -35,6 +35,10 @@ void launch_step(const Work& w, Mode mode, unsigned phase, hipStream_t s);
 // dsmc_profile_step.
 void launch_step_timed(const Work& w, Mode mode, unsigned phase, hipStream_t s, hipEvent_t* ev);
 void launch_finalize(const InstDesc* d_desc, int n_inst, hipStream_t s);
+// Estimators of n_inst instances into stage: instance b at d_off[b], its
+// kEstPerCell * C + 3 values followed by its status word.
+void launch_finalize_staged(const InstDesc* d_desc, const int64_t* d_off, double* d_stage,
+                            int n_inst, hipStream_t s);
 void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s);
 size_t fast_collide_lds_bytes(Mode mode, int cap);
 size_t bucket_collide_lds_bytes(Mode mode, int cap);

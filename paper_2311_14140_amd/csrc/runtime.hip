@@ -250,6 +250,18 @@ struct dsmc_group {
     int n_lanes = 1;     // lanes in use (lanes.size() may be larger)
     std::vector<Lane> lanes;
     hipEvent_t fork = nullptr;
+    // dsmc_group_sample: the members' descriptors and staging-block offsets
+    // in member order, the device staging buffer and its pinned host mirror,
+    // rebuilt when the membership changes
+    uint64_t version = 0;            // bumped by every add / remove
+    uint64_t sample_version = ~0ull;
+    InstDesc* d_sdesc = nullptr;
+    int64_t* d_soff = nullptr;
+    double* d_stage = nullptr;
+    double* h_stage = nullptr;
+    size_t sdesc_cap = 0, stage_cap = 0;   // members / doubles allocated
+    size_t stage_doubles = 0;
+    std::vector<int64_t> soff;
     std::string err;
 };
 
@@ -585,7 +597,54 @@ void group_free(dsmc_group* g) {
         if (l.d_mem) (void)hipFree(l.d_mem);
     }
     if (g->fork) (void)hipEventDestroy(g->fork);
+    if (g->d_sdesc) (void)hipFree(g->d_sdesc);
+    if (g->d_soff) (void)hipFree(g->d_soff);
+    if (g->d_stage) (void)hipFree(g->d_stage);
+    if (g->h_stage) (void)hipHostFree(g->h_stage);
     delete g;
+}
+
+// Staging of dsmc_group_sample for the current members: member i's block of
+// kEstPerCell * C + 4 doubles (estimators, mass flow, sampled steps,
+// collisions, status) starts at soff[i], rounded up to 32 doubles.
+int prepare_group_sample(dsmc_group* g) {
+    if (g->sample_version == g->version) return DSMC_OK;
+    const size_t n = g->members.size();
+    g->soff.assign(n, 0);
+    size_t tot = 0;
+    for (size_t i = 0; i < n; ++i) {
+        g->soff[i] = (int64_t)tot;
+        tot += ((size_t)kEstPerCell * g->members[i]->plan.C + 4 + 31) & ~(size_t)31;
+    }
+    if (n > g->sdesc_cap) {
+        if (g->d_sdesc) (void)hipFree(g->d_sdesc);
+        if (g->d_soff) (void)hipFree(g->d_soff);
+        g->d_sdesc = nullptr;
+        g->d_soff = nullptr;
+        g->sdesc_cap = 0;
+        if (hipMalloc((void**)&g->d_sdesc, n * sizeof(InstDesc)) != hipSuccess ||
+            hipMalloc((void**)&g->d_soff, n * sizeof(int64_t)) != hipSuccess)
+            return fail(&g->err, DSMC_ERR_OUT_OF_MEMORY, "group sample descriptors");
+        g->sdesc_cap = n;
+    }
+    if (tot > g->stage_cap) {
+        if (g->d_stage) (void)hipFree(g->d_stage);
+        if (g->h_stage) (void)hipHostFree(g->h_stage);
+        g->d_stage = nullptr;
+        g->h_stage = nullptr;
+        g->stage_cap = 0;
+        if (hipMalloc((void**)&g->d_stage, tot * sizeof(double)) != hipSuccess ||
+            hipHostMalloc((void**)&g->h_stage, tot * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return fail(&g->err, DSMC_ERR_OUT_OF_MEMORY, "group sample staging");
+        g->stage_cap = tot;
+    }
+    std::vector<InstDesc> hd(n);
+    for (size_t i = 0; i < n; ++i) hd[i] = g->members[i]->desc;
+    HIP_TRY(&g->err, hipMemcpy(g->d_sdesc, hd.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice));
+    HIP_TRY(&g->err, hipMemcpy(g->d_soff, g->soff.data(), n * sizeof(int64_t), hipMemcpyHostToDevice));
+    g->stage_doubles = tot;
+    g->sample_version = g->version;
+    return DSMC_OK;
 }
 
 }  // namespace
@@ -978,6 +1037,7 @@ int dsmc_group_add(dsmc_group* g, dsmc_handle* h) {
     g->members.push_back(h);
     h->group = g;
     g->dirty = true;
+    ++g->version;
     return DSMC_OK;
 }
 
@@ -989,6 +1049,7 @@ int dsmc_group_remove(dsmc_group* g, dsmc_handle* h) {
     g->members.erase(it);
     h->group = nullptr;
     g->dirty = true;
+    ++g->version;
     return DSMC_OK;
 }
 
@@ -1008,6 +1069,57 @@ int dsmc_group_sync(dsmc_group* g) {
         if (r) return r;
     }
     return DSMC_OK;
+}
+
+int dsmc_group_sample(dsmc_group* g, dsmc_moments* outs, int32_t n_outs, int reset_window) {
+    if (!g || (!outs && n_outs)) return fail(g ? &g->err : nullptr, DSMC_ERR_INVALID_ARG, "NULL argument");
+    const int n = (int)g->members.size();
+    if (n_outs != n) return fail(&g->err, DSMC_ERR_INVALID_ARG, "n_outs differs from the group's member count");
+    if (n == 0) return DSMC_OK;
+    for (int i = 0; i < n; ++i) {
+        if (outs[i].n_cells < g->members[i]->plan.C)
+            return fail(&g->err, DSMC_ERR_INVALID_ARG, "moments.n_cells smaller than a member's cells");
+        if (outs[i].raw_sums)
+            return fail(&g->err, DSMC_ERR_INVALID_ARG, "raw sums are returned by dsmc_sample only");
+    }
+    int r = prepare_group_sample(g);
+    if (r) return r;
+    hipStream_t s = g->stream;
+    launch_finalize_staged(g->d_sdesc, g->d_soff, g->d_stage, n, s);
+    HIP_TRY(&g->err, hipGetLastError());
+    HIP_TRY(&g->err, hipMemcpyAsync(g->h_stage, g->d_stage, g->stage_doubles * sizeof(double),
+                                    hipMemcpyDeviceToHost, s));
+    if (reset_window) {
+        launch_reset_window(g->d_sdesc, n, s);
+        HIP_TRY(&g->err, hipGetLastError());
+    }
+    HIP_TRY(&g->err, hipStreamSynchronize(s));
+    int rc = DSMC_OK;
+    for (int i = 0; i < n; ++i) {
+        const int C = g->members[i]->plan.C;
+        const double* e = g->h_stage + g->soff[i];
+        dsmc_moments* out = &outs[i];
+        const int status = (int)e[(size_t)kEstPerCell * C + 3];
+        if (status) {
+            out->n_sampled_steps = -1;
+            if (rc == DSMC_OK) {
+                const char* why = (status & 1)   ? "non-finite particle velocity"
+                                  : (status & 2) ? "cell counts do not add up to N"
+                                                 : "sorted slot out of range";
+                rc = fail(&g->err, DSMC_ERR_NUMERIC, "member " + std::to_string(i) + ": " + why);
+            }
+            continue;
+        }
+        double* dst[kEstPerCell] = {out->n,  out->ux, out->uy, out->uz,     out->T,
+                                    out->pxy, out->qx, out->qy, out->pxy_mid};
+        for (int m = 0; m < kEstPerCell; ++m)
+            if (dst[m]) std::memcpy(dst[m], e + (size_t)m * C, sizeof(double) * C);
+        const double K = e[(size_t)kEstPerCell * C + 1];
+        out->n_sampled_steps = (int64_t)K;
+        out->mass_flow = K > 0 ? e[(size_t)kEstPerCell * C] : NAN;
+        out->n_collisions = (int64_t)e[(size_t)kEstPerCell * C + 2];
+    }
+    return rc;
 }
 
 int dsmc_group_size(const dsmc_group* g, int32_t* n) {

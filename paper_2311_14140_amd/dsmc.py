@@ -36,7 +36,7 @@ EXPORTS = (
     "dsmc_set_cells", "dsmc_info", "dsmc_status_string", "dsmc_last_error",
     "dsmc_group_create", "dsmc_group_add", "dsmc_group_remove", "dsmc_group_step",
     "dsmc_group_sync", "dsmc_group_size", "dsmc_group_lanes", "dsmc_group_destroy", "dsmc_group_set_tuning",
-    "dsmc_group_autotune", "dsmc_profile_step",
+    "dsmc_group_autotune", "dsmc_profile_step", "dsmc_group_sample",
 )
 
 
@@ -92,6 +92,7 @@ def _load():
         "dsmc_group_sync": [vp],
         "dsmc_group_size": [vp, ct.POINTER(i32)],
         "dsmc_group_lanes": [vp, ct.POINTER(i32)],
+        "dsmc_group_sample": [vp, vp, i32, ct.c_int],
         "dsmc_group_destroy": [vp],
         "dsmc_group_set_tuning": [vp, i32, i32],
         "dsmc_group_autotune": [vp, ct.POINTER(i32), ct.POINTER(i32)],
@@ -312,6 +313,27 @@ class Group:
 
     def sync(self):
         _check(lib.dsmc_group_sync(self._g))
+
+    def sample(self, reset: bool = False) -> list:
+        """Every member's window estimators (as ``Solver.sample`` without raw
+        sums), in member order, with one launch, one copy and one
+        synchronisation for the whole group."""
+        n = len(self.members)
+        ms = (dsmc_moments * max(n, 1))()
+        outs = []
+        for i, s in enumerate(self.members):
+            arrs = {k: np.zeros(s.C) for k in ("n", "ux", "uy", "uz", "T", "pxy", "qx", "qy",
+                                                 "pxy_mid")}
+            ms[i].n_cells = s.C
+            for k, a in arrs.items():
+                setattr(ms[i], k, a.ctypes.data_as(_dp))
+            outs.append(arrs)
+        _check(lib.dsmc_group_sample(self._g, ms, n, 1 if reset else 0))
+        for i, arrs in enumerate(outs):
+            arrs["mass_flow"] = ms[i].mass_flow
+            arrs["n_sampled_steps"] = ms[i].n_sampled_steps
+            arrs["n_collisions"] = ms[i].n_collisions
+        return outs
 
     def lanes(self) -> int:
         """Lanes the members ran in at the last step (each kernel of a step is

@@ -68,8 +68,8 @@ def run_benchmark(params_list, sampling_steps: int, n_batches: int = 20) -> Benc
         ux, pxy, q = [], [], []
         for _ in range(n_batches):
             _advance(solvers, group, per)
-            for s in solvers:
-                w = s.sample(reset=True)
+            ws = group.sample(reset=True) if group is not None else [s.sample(reset=True) for s in solvers]
+            for w in ws:
                 if w["n_sampled_steps"] != per:
                     raise RuntimeError("benchmark window shorter than asked")
                 ux.append(w["ux"])

@@ -270,17 +270,23 @@ def collect_windows(solvers, n_windows: int, steps_per_sample: int = 100, group=
     the momentum flux).
 
     ``solvers`` are ``dsmc.Solver`` objects past their transient; with
-    ``group`` (a ``dsmc.Group`` holding them all) one group step advances them
-    together.  Returns the seconds spent stepping+sampling."""
+    ``group`` (a ``dsmc.Group`` holding exactly them, in order) one group
+    step advances them together and one group call takes all their windows.
+    Returns the seconds spent stepping and sampling."""
     t0 = time.perf_counter()
+    if group is not None and list(group.members) != list(solvers):
+        raise ValueError("the group must hold exactly the solvers, in order")
     for _ in range(n_windows):
         if group is not None:
             group.step(steps_per_sample)
+            ws = group.sample(reset=True)
         else:
+            ws = []
             for s in solvers:
                 s.step(steps_per_sample)
-        for k, s in enumerate(solvers):
-            w = s.sample(reset=True)
+            for s in solvers:
+                ws.append(s.sample(reset=True))
+        for k, w in enumerate(ws):
             if w["n_sampled_steps"] != steps_per_sample:
                 raise RuntimeError(f"window of {w['n_sampled_steps']} sampled steps, "
                                    f"expected {steps_per_sample} (transient not over?)")

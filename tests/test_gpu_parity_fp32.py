@@ -510,3 +510,62 @@ def test_time_centred_stress_keeps_the_momentum_balance(D):
         m, se = slopes.mean(), slopes.std(ddof=1) / math.sqrt(R)
         print(f"{k}: slope/(2F) {m:.4f} +- {se:.4f} (expected {want:.4f})", flush=True)
         assert abs(m - want) < 4 * se + 0.005
+
+
+def _same_window(a, b):
+    for k in ("n", "ux", "uy", "uz", "T", "pxy", "qx", "qy", "pxy_mid"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    for k in ("n_sampled_steps", "n_collisions"):
+        assert a[k] == b[k], k
+    assert a["mass_flow"] == b["mass_flow"] or (math.isnan(a["mass_flow"]) and math.isnan(b["mass_flow"]))
+
+
+@pytest.mark.parametrize("two_lanes", [False, True])
+def test_group_sample_equals_member_samples(D, two_lanes):
+    """One group call returns every member's window exactly as its own
+    dsmc_sample does, resets every window, and follows membership changes."""
+    import ctypes as ct
+    if two_lanes:
+        ps = [Params(kn=0.3, body_force=0.01, n_cells=600, particles_per_cell=2500, seed=51,
+                     n_transient=3, precision=D.DSMC_FP32_FAST),
+              Params(kn=2.0, body_force=0.005, n_cells=800, particles_per_cell=100, seed=52,
+                     n_transient=3, precision=D.DSMC_FP32_FAST),
+              Params(kn=0.08, body_force=0.02, n_cells=400, particles_per_cell=1500, seed=53,
+                     n_transient=3, precision=D.DSMC_FP32_FAST)]
+    else:
+        ps = [Params(kn=10 ** (-1 + 0.2 * i), body_force=0.01, n_cells=50 + 37 * i,
+                     particles_per_cell=20 + 13 * i, seed=60 + i, n_transient=2,
+                     precision=D.DSMC_FP32_FAST) for i in range(9)]
+    sols = [D.Solver(p) for p in ps]
+    g = D.Group()
+    for s in sols:
+        g.add(s)
+    g.step(11)
+    if two_lanes:
+        assert g.lanes() == 2
+    gs = g.sample()
+    assert len(gs) == len(sols)
+    for s, w in zip(sols, gs):
+        _same_window(w, s.sample())
+    again = g.sample(reset=True)
+    for w, v in zip(gs, again):
+        _same_window(w, v)
+    for w in g.sample():
+        assert w["n_sampled_steps"] == 0 and math.isnan(w["mass_flow"])
+    g.step(5)
+    for s, w in zip(sols, g.sample()):
+        assert w["n_sampled_steps"] == 5
+        _same_window(w, s.sample())
+    # membership change: the staging follows the member order
+    g.remove(sols[1])
+    g.step(3)
+    rest = [s for s in sols if s is not sols[1]]
+    for s, w in zip(rest, g.sample()):
+        assert w["n_sampled_steps"] == 8
+        _same_window(w, s.sample())
+    # a wrong member count is refused
+    m = (D.dsmc_moments * len(rest))()
+    assert D.lib.dsmc_group_sample(g._g, m, len(rest) + 1, 0) == D.DSMC_ERR_INVALID_ARG
+    g.close()
+    for s in sols:
+        s.close()
