@@ -1221,6 +1221,30 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
     }
 }
 
+// Group sums by recursive halving.  A group of G lanes holds per-lane
+// partials of the sampling sums, padded to kHalvingMoments.  At each exchange
+// distance off (G/2, G/4, ...) a lane keeps the half of its moments selected
+// by its lane bit, adds its partner's copy of that half and passes the other
+// half on; first tracks which moments the lane keeps.  The pairs added are
+// the pairs of a full xor butterfly, so every total is the same to the bit,
+// but a lane exchanges 8 + 4 + 2 + 1 moments rather than all of them at every
+// distance, and the totals end on different lanes, which issue their
+// atomics in parallel.
+constexpr int kHalvingMoments = 16;
+static_assert(kMoments <= kHalvingMoments, "the halving covers every moment");
+
+template <int H>
+__device__ __forceinline__ void halve(double* r, int off, bool upper, int& first) {
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const double lo = r[k], hi = r[k + H];
+        const double pass = upper ? lo : hi;
+        const double keep = upper ? hi : lo;
+        r[k] = keep + __shfl_xor(pass, off, 64);
+    }
+    if (upper) first += H;
+}
+
 // NTC of small cells by groups of G lanes (G = 4..64, a power of two fixed
 // per instance and launch shape): each group of a wavefront owns one cell at
 // a time and runs that cell's candidates in rounds of G, with a claim table
@@ -1316,19 +1340,36 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
             const double other = __shfl_xor(mx, off, 64);
             mx = other > mx ? other : mx;
             cc += __shfl_xor(cc, off, 64);
-#pragma unroll
-            for (int k = 0; k < kMoments; ++k) m.s[k] += __shfl_xor(m.s[k], off, 64);
         }
-        if (has && (lane & (G - 1)) == 0) {
-            if (do_collide && nc >= 2) {
-                d.rem[c] = mreal - mf;
-                if (mx > crm0) d.crmax[c] = mx;
-                if (cc) atomicAdd(&d.ncoll[c], cc);
-            }
-            if (sample) {
+        const int gl = lane & (G - 1);
+        if (has && gl == 0 && do_collide && nc >= 2) {
+            d.rem[c] = mreal - mf;
+            if (mx > crm0) d.crmax[c] = mx;
+            if (cc) atomicAdd(&d.ncoll[c], cc);
+        }
+        if (sample) {
+            // the moment sums by recursive halving: lane gl ends with the
+            // group's totals of moments first .. first + held - 1
+            double r[kHalvingMoments];
+#pragma unroll
+            for (int k = 0; k < kHalvingMoments; ++k) r[k] = k < kMoments ? m.s[k] : 0.0;
+            int first = 0, off = G >> 1;
+            if (off >= 1) { halve<8>(r, off, (gl & off) != 0, first); off >>= 1; }
+            if (off >= 1) { halve<4>(r, off, (gl & off) != 0, first); off >>= 1; }
+            if (off >= 1) { halve<2>(r, off, (gl & off) != 0, first); off >>= 1; }
+            if (off >= 1) { halve<1>(r, off, (gl & off) != 0, first); off >>= 1; }
+            // groups wider than kHalvingMoments finish with full exchanges,
+            // after which lanes differing only in the low bits hold the same
+            // totals: the one with those bits clear adds them
+            const int dup = G > kHalvingMoments ? G / kHalvingMoments - 1 : 0;
+            for (; off >= 1; off >>= 1) r[0] += __shfl_xor(r[0], off, 64);
+            if (has && (gl & dup) == 0) {
+                const int held = G >= kHalvingMoments ? 1 : kHalvingMoments / G;
                 double* a = d.acc + c;
 #pragma unroll
-                for (int k = 0; k < kMoments; ++k) unsafeAtomicAdd(&a[(size_t)k * d.Cc], m.s[k]);
+                for (int k = 0; k < kHalvingMoments / 2; ++k)
+                    if (k < held && first + k < kMoments)
+                        unsafeAtomicAdd(&a[(size_t)(first + k) * d.Cc], r[k]);
             }
         }
     }

@@ -569,3 +569,29 @@ def test_group_sample_equals_member_samples(D, two_lanes):
     g.close()
     for s in sols:
         s.close()
+
+
+@pytest.mark.parametrize("prec_name", ["DSMC_FP32_FAST", "DSMC_FP64_FAST"])
+@pytest.mark.parametrize("ppc", [20, 70, 100, 200, 400])
+def test_moment_sums_match_the_particle_state(D, prec_name, ppc):
+    """With the collide phase off, one sampled step's thirteen sums per cell
+    are sums over the particles the state holds in that cell (recomputed
+    here in FP64 from the returned velocities): every moment, for cell sizes
+    whose lane groups span G = 4 to 64 and the whole-workgroup path."""
+    prec = getattr(D, prec_name)
+    p = Params(kn=0.5, body_force=0.02, n_cells=40, particles_per_cell=ppc, seed=71,
+               n_transient=0, precision=prec)
+    mask = D.DSMC_PHASE_MOVE | D.DSMC_PHASE_SORT | D.DSMC_PHASE_SAMPLE
+    with D.Solver(p, debug_phase_mask=mask) as s:
+        s.step(1)
+        raw = s.sample(raw=True)["raw"]
+        y, vx, vy, vz, cell, _ = s.get_state()
+    vx, vy, vz = (np.asarray(a, dtype=np.float64) for a in (vx, vy, vz))
+    v2 = vx * vx + vy * vy + vz * vz
+    terms = [np.ones_like(vx), vx, vy, vz, vx * vx, vy * vy, vz * vz, vx * vy, vx * vz, vy * vz,
+             v2 * vx, v2 * vy, vx * vy]
+    cell = np.asarray(cell)
+    for k, t in enumerate(terms):
+        want = np.bincount(cell, weights=t, minlength=raw.shape[0])
+        scale = np.bincount(cell, weights=np.abs(t), minlength=raw.shape[0])
+        assert np.all(np.abs(raw[:, k] - want) <= 1e-12 * scale + 1e-300), k
