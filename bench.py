@@ -53,8 +53,8 @@ def kernel_bytes(phase: str, N: int, Cc: int, rb: int, coll_frac: float, samplin
         else:                    # read v, write v back
             b = N * 6 * rb
         b += Cc * (8 + 8 + 4 + 4 + 4)  # crmax, rem, count, offset, collisions
-        if sampling:
-            b += Cc * 12 * 8 * 2
+        if sampling:             # thirteen FP64 sums per cell, read and written
+            b += Cc * 13 * 8 * 2
         return b
     if phase == "scan":
         return Cc * 4 * 2
