@@ -45,7 +45,8 @@ class _Params(ct.Structure):
                 ("wall_temperature", ct.c_double), ("dt", ct.c_double),
                 ("n_cells", ct.c_int32), ("particles_per_cell", ct.c_int32),
                 ("n_sub", ct.c_int32), ("pad_", ct.c_int32),
-                ("n_transient", ct.c_int64), ("seed", ct.c_uint64)]
+                ("n_transient", ct.c_int64), ("seed", ct.c_uint64),
+                ("domain_length", ct.c_double)]
 
 
 def _dp():
@@ -67,6 +68,11 @@ def lib():
             L.or_estimators.argtypes = [vp] + [vp] * 10
             L.or_n_particles.restype = ct.c_int32
             L.or_n_particles.argtypes = [vp]
+            L.or_capacity.restype = ct.c_int32
+            L.or_capacity.argtypes = [vp]
+            L.or_set_inflow.argtypes = [vp, ct.c_double, ct.c_double, ct.c_double, ct.c_double]
+            L.or_open_diagnostics.argtypes = [vp, vp]
+            L.or_inject_one.argtypes = [vp, ct.c_int64, ct.c_int64, vp]
             L.or_n_coll_cells.restype = ct.c_int32
             L.or_n_coll_cells.argtypes = [vp]
             L.or_step_index.restype = ct.c_int64
@@ -156,15 +162,15 @@ class Oracle:
                     wall_temperature=params.wall_temperature, dt=params.dt,
                     n_cells=params.n_cells, particles_per_cell=params.particles_per_cell,
                     n_sub=params.n_sub, pad_=0, n_transient=params.n_transient,
-                    seed=params.seed)
+                    seed=params.seed, domain_length=getattr(params, "domain_length", 0.0))
         self._L = lib()
         h = self._L.or_create(ct.byref(p))
         if not h:
             raise ValueError("invalid oracle parameters")
         self._h = ct.c_void_p(h)
         self.params = params
-        self.N = self._L.or_n_particles(self._h)
         self.Cc = self._L.or_n_coll_cells(self._h)
+        self.capacity = self._L.or_capacity(self._h)
         self.C = params.n_cells
 
     def close(self):
@@ -191,6 +197,29 @@ class Oracle:
 
     def reset_window(self):
         self._L.or_reset_window(self._h)
+
+    @property
+    def N(self) -> int:
+        """Particles in the domain (changes with each step of an open domain)."""
+        return self._L.or_n_particles(self._h)
+
+    def set_inflow(self, u=0.0, dudy=0.0, T=1.0, n=1.0):
+        """Chapman-Enskog inflow state at the open boundary (u, du/dy in the
+        units of Eq. 6; T and n relative to the reference state)."""
+        self._L.or_set_inflow(self._h, float(u), float(dudy), float(T), float(n))
+
+    def inject_one(self, step: int, k: int) -> np.ndarray:
+        """Particle k injected at the start of step ``step``: (y, vx, vy, vz)
+        before that step's move, in code units."""
+        st = np.zeros(4)
+        self._L.or_inject_one(self._h, int(step), int(k), _ptr(st))
+        return st
+
+    def open_diagnostics(self) -> dict:
+        o = np.zeros(5)
+        self._L.or_open_diagnostics(self._h, _ptr(o))
+        return dict(n_live=int(o[0]), n_injected=int(o[1]), n_deleted=int(o[2]),
+                    status=int(o[3]), inj_rem=float(o[4]))
 
     def particles(self):
         n = self.N

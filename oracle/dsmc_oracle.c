@@ -55,6 +55,9 @@
 #define TAG_INIT 1u
 #define TAG_WALL 2u
 #define TAG_COLL 3u
+#define TAG_INJECT 5u
+
+static const double PI = 0x1.921fb54442d18p+1; /* pi, correctly rounded */
 
 #define PHASE_MOVE 1u
 #define PHASE_SORT 2u
@@ -76,14 +79,26 @@ typedef struct or_params {
     int32_t pad_;
     int64_t n_transient;
     uint64_t seed;
+    double domain_length; /* 0: the closed gap [0, H]; L in (0, H]: a wall at 0 and
+                             an open boundary at L (a DSMC patch of the hybrid) */
 } or_params;
 
 typedef struct or_state {
     or_params p;
     int32_t C;    /* sampling cells */
     int32_t Cc;   /* collision cells = C * n_sub */
-    int32_t N;    /* particles */
-    double H, lam, dt, g, kntc, crmax0, sqrt_tw, inv_dy;
+    int32_t N;    /* particles in the domain (after the last sort) */
+    int32_t Nnom; /* nominal particles: C * ppc, the initial count */
+    int32_t Ncap; /* slots allocated (open domains hold a margin above Nnom) */
+    int32_t Nused;/* slots holding particles during a step: N plus those injected */
+    int open;     /* 1 if the top of the domain is an open boundary */
+    double H, L, lam, dt, g, kntc, crmax0, sqrt_tw, inv_dy;
+    /* inflow at the open boundary: mean x velocity (code units), sqrt(T),
+     * thermal speed sqrt(2T), the Chapman-Enskog shear weight a and its
+     * bound A, particles expected to enter per step and the carried remainder */
+    double u_in, sqrt_tin, vt_in, ce_a, ce_A, inj_expected, inj_rem;
+    int64_t n_injected, n_deleted;
+    int32_t status;     /* bit 0: an injection needed more slots than allocated */
     uint32_t key[2];
     double *y, *vx, *vy, *vz;
     int32_t *cell;
@@ -287,6 +302,8 @@ static int params_valid(const or_params *p)
     if ((int64_t)p->n_cells * (int64_t)p->particles_per_cell > 2147483647) return 0;
     if ((int64_t)p->n_cells * (int64_t)p->n_sub > 2147483647) return 0;
     if (p->n_transient < 0) return 0;
+    if (!(isfinite(p->domain_length) && p->domain_length >= 0.0 && p->domain_length <= 1.0))
+        return 0;
     return 1;
 }
 
@@ -304,7 +321,7 @@ void or_destroy(or_state *S)
 static void init_particles(or_state *S)
 {
     const int32_t ppc = S->p.particles_per_cell;
-    const double dy = S->H / (double)S->C;
+    const double dy = S->L / (double)S->C;
     for (int32_t p = 0; p < S->N; ++p) {
         int32_t c = p / ppc;
         stream s = make_stream(S->key, 0, p, 0, TAG_INIT);
@@ -323,6 +340,8 @@ static void init_particles(or_state *S)
     }
 }
 
+void or_set_inflow(or_state *S, double u, double dudy, double T, double n);
+
 or_state *or_create(const or_params *p)
 {
     if (!p || !params_valid(p)) return NULL;
@@ -332,8 +351,21 @@ or_state *or_create(const or_params *p)
     S->C = p->n_cells;
     S->Cc = p->n_cells * p->n_sub;
     S->N = p->n_cells * p->particles_per_cell;
+    S->Nnom = S->N;
+    S->open = p->domain_length > 0.0;
+    /* an open domain's count fluctuates about Nnom: room for 25% more, and at
+     * least 8 standard deviations plus 64 */
+    S->Ncap = S->N;
+    if (S->open) {
+        int64_t m1 = (int64_t)S->N / 4, m2 = (int64_t)(8.0 * sqrt((double)S->N)) + 64;
+        int64_t cap = (int64_t)S->N + (m1 > m2 ? m1 : m2);
+        if (cap > 2147483647) return NULL;
+        S->Ncap = (int32_t)cap;
+    }
+    S->Nused = S->N;
     /* Constants, each evaluated once in double, left to right. */
     S->H = 1.0;
+    S->L = S->open ? p->domain_length : S->H;
     S->lam = p->kn * S->H;
     if (p->dt > 0.0) {
         S->dt = p->dt;
@@ -345,11 +377,11 @@ or_state *or_create(const or_params *p)
     S->kntc = (S->dt * (double)p->n_sub) / ((sqrt(2.0) * S->lam) * (double)p->particles_per_cell);
     S->crmax0 = 5.0 * sqrt(2.0 * p->wall_temperature);
     S->sqrt_tw = sqrt(p->wall_temperature);
-    S->inv_dy = (double)S->Cc / S->H;
+    S->inv_dy = (double)S->Cc / S->L;
     S->key[0] = (uint32_t)(p->seed & 0xFFFFFFFFu);
     S->key[1] = (uint32_t)(p->seed >> 32);
 
-    size_t n = (size_t)S->N, cc = (size_t)S->Cc;
+    size_t n = (size_t)S->Ncap, cc = (size_t)S->Cc;
     S->y = malloc(n * sizeof(double));
     S->vx = malloc(n * sizeof(double));
     S->vy = malloc(n * sizeof(double));
@@ -362,8 +394,8 @@ or_state *or_create(const or_params *p)
     S->tcell = malloc(n * sizeof(int32_t));
     S->crmax = malloc(cc * sizeof(double));
     S->rem = malloc(cc * sizeof(double));
-    S->count = malloc(cc * sizeof(int32_t));
-    S->offset = malloc(cc * sizeof(int32_t));
+    S->count = malloc((cc + 1) * sizeof(int32_t));
+    S->offset = malloc((cc + 1) * sizeof(int32_t));
     S->acc = calloc(cc * NMOM, sizeof(double));
     if (!S->y || !S->vx || !S->vy || !S->vz || !S->cell || !S->ty || !S->tvx ||
         !S->tvy || !S->tvz || !S->tcell || !S->crmax || !S->rem || !S->count ||
@@ -372,6 +404,7 @@ or_state *or_create(const or_params *p)
         return NULL;
     }
     init_particles(S);
+    or_set_inflow(S, 0.0, 0.0, p->wall_temperature, 1.0);
     return S;
 }
 
@@ -382,16 +415,17 @@ or_state *or_create(const or_params *p)
  * parallel to them).  The wall draw for the h-th hit of slot p in step s uses
  * tag WALL, entity p, sub-index h: call 0 gives the normal speed (Rayleigh,
  * sqrt(-2 T_w ln U)), later calls a polar normal pair for (vx, vz). */
-static void move_one(or_state *S, int64_t step, int64_t slot, double *py, double *pvx,
-                     double *pvy, double *pvz)
+static int move_one(or_state *S, int64_t step, int64_t slot, double *py, double *pvx,
+                    double *pvy, double *pvz)
 {
     double y = *py, vx = *pvx, vy = *pvy, vz = *pvz;
     double t = S->dt;
     int64_t h = 0;
+    int gone = 0;
     for (;;) {
         double tw;
         if (vy > 0.0)
-            tw = (S->H - y) / vy;
+            tw = (S->L - y) / vy;
         else if (vy < 0.0)
             tw = (0.0 - y) / vy;
         else
@@ -402,6 +436,13 @@ static void move_one(or_state *S, int64_t step, int64_t slot, double *py, double
             break;
         }
         int top = vy > 0.0;
+        if (top && S->open) {
+            /* leaves through the open boundary */
+            y = S->L;
+            vx = vx + S->g * tw;
+            gone = 1;
+            break;
+        }
         double vx_hit = vx + S->g * tw;
         double e_hit = (vx_hit * vx_hit + vy * vy) + vz * vz;
         y = top ? S->H : 0.0;
@@ -419,11 +460,12 @@ static void move_one(or_state *S, int64_t step, int64_t slot, double *py, double
         h += 1;
     }
     if (y < 0.0) y = 0.0;
-    if (y > S->H) y = S->H;
+    if (y > S->L) y = S->L;
     *py = y;
     *pvx = vx;
     *pvy = vy;
     *pvz = vz;
+    return gone;
 }
 
 static int32_t cell_of(const or_state *S, double y)
@@ -433,11 +475,97 @@ static int32_t cell_of(const or_state *S, double y)
     return c;
 }
 
+/* --------------------------------------------------------------- inflow */
+/* Inflow state at the open boundary (the paper's hybrid imposes the
+ * Chapman-Enskog distribution at the local macro state there, Sec. 2 and
+ * Sec. 3.2): u and du/dy in the units of Eq. 6, T over T_ref, n over the
+ * nominal density.  For pure shear the Chapman-Enskog factor is
+ * 1 - a C_x C_y with C = (c - u)/sqrt(2T) and a = -2 P_xy / (n T), where
+ * Newton's law gives P_xy = -(2 Kn/sqrt(pi)) sqrt(T) du/dy for hard spheres
+ * (viscosity ~ sqrt(T)); so a = (4 Kn/sqrt(pi)) du/dy / (n sqrt(T)).  The
+ * inward number flux is the Maxwellian one, n sqrt(T/(2 pi)) per unit area
+ * and time in these units (the shear term carries no net number flux). */
+void or_set_inflow(or_state *S, double u, double dudy, double T, double n)
+{
+    S->u_in = u * sqrt(2.0);
+    S->sqrt_tin = sqrt(T);
+    S->vt_in = sqrt(2.0 * T);
+    S->ce_a = (((4.0 * S->p.kn) / sqrt(PI)) * dudy) / (n * S->sqrt_tin);
+    S->ce_A = 1.0 + 16.0 * fabs(S->ce_a);
+    S->inj_expected = ((n * ((double)S->Nnom / S->L)) * sqrt(T / (2.0 * PI))) * S->dt;
+}
+
+/* Particles entering through the open boundary at the start of a step:
+ * floor(expected + carried remainder) of them, appended after the N live
+ * slots.  Particle k of step s draws from tag INJECT, entity k: per attempt
+ * one call gives the acceptance uniform and the flux-weighted inward speed
+ * sqrt(-2 T ln U), a polar pair from the following calls gives the thermal
+ * x and z velocities, and the attempt is kept with probability
+ * (1 - a C_x C_y) / A; a last call gives the time fraction U of the step it
+ * spends inside.  It is placed where a straight flight of the whole step
+ * brings it across the boundary at that time, beyond the boundary, with the
+ * force's x velocity gain of the outside part taken off, so that the
+ * ordinary move delivers it with the drawn velocity at the boundary.
+ * Returns the number injected. */
+void or_inject_one(const or_state *S, int64_t step, int64_t k, double st[4])
+{
+    stream s = make_stream(S->key, step, k, 0, TAG_INJECT);
+    double sp, tx, tz;
+    for (;;) {
+        double ua, ub;
+        stream_uniform2(&s, &ua, &ub);
+        sp = sqrt(-2.0 * or_log(ub)) * S->sqrt_tin;
+        stream_normal2(&s, S->sqrt_tin, &tx, &tz);
+        double cx = tx / S->vt_in;
+        double cy = -sp / S->vt_in;
+        double gam = 1.0 - S->ce_a * (cx * cy);
+        if (ua * S->ce_A < gam) break;
+    }
+    double ut, unused;
+    stream_uniform2(&s, &ut, &unused);
+    double outside = S->dt - ut * S->dt;
+    st[0] = S->L + sp * outside;
+    st[1] = (S->u_in + tx) - S->g * outside;
+    st[2] = -sp;
+    st[3] = tz;
+}
+
+static int32_t inject(or_state *S, int64_t step)
+{
+    double m = S->inj_expected + S->inj_rem;
+    double f = floor(m);
+    S->inj_rem = m - f;
+    int64_t n = (int64_t)f;
+    if ((int64_t)S->N + n > (int64_t)S->Ncap) {
+        S->status |= 1;
+        n = (int64_t)S->Ncap - (int64_t)S->N;
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        double st[4];
+        or_inject_one(S, step, k, st);
+        int32_t q = S->N + (int32_t)k;
+        S->y[q] = st[0];
+        S->vx[q] = st[1];
+        S->vy[q] = st[2];
+        S->vz[q] = st[3];
+        S->cell[q] = 0;
+    }
+    S->n_injected += n;
+    return (int32_t)n;
+}
+
+/* Move every slot; a particle that leaves through the open boundary gets the
+ * key Cc, after every cell, so that the sort gathers the removed particles
+ * past the live ones. */
 static void phase_move(or_state *S, int64_t step)
 {
-    for (int32_t p = 0; p < S->N; ++p) {
-        move_one(S, step, p, &S->y[p], &S->vx[p], &S->vy[p], &S->vz[p]);
-        S->cell[p] = cell_of(S, S->y[p]);
+    int32_t n = S->N;
+    if (S->open) n += inject(S, step);
+    S->Nused = n;
+    for (int32_t p = 0; p < n; ++p) {
+        int gone = move_one(S, step, p, &S->y[p], &S->vx[p], &S->vy[p], &S->vz[p]);
+        S->cell[p] = gone ? S->Cc : cell_of(S, S->y[p]);
+        S->n_deleted += gone;
     }
 }
 
@@ -463,9 +591,10 @@ void or_stable_sort_perm(int32_t n, const int32_t *key, int32_t nkeys, int32_t *
 
 static void phase_sort(or_state *S)
 {
-    int32_t *perm = (int32_t *)malloc((size_t)S->N * sizeof(int32_t));
-    or_stable_sort_perm(S->N, S->cell, S->Cc, S->count, S->offset, perm);
-    for (int32_t d = 0; d < S->N; ++d) {
+    const int32_t n = S->Nused;
+    int32_t *perm = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    or_stable_sort_perm(n, S->cell, S->Cc + S->open, S->count, S->offset, perm);
+    for (int32_t d = 0; d < n; ++d) {
         int32_t s = perm[d];
         S->ty[d] = S->y[s];
         S->tvx[d] = S->vx[s];
@@ -480,6 +609,9 @@ static void phase_sort(or_state *S)
     t = S->vz; S->vz = S->tvz; S->tvz = t;
     int32_t *tc = S->cell; S->cell = S->tcell; S->tcell = tc;
     free(perm);
+    /* the removed particles sit past the live ones */
+    if (S->open) S->N = S->offset[S->Cc];
+    S->Nused = S->N;
 }
 
 /* ------------------------------------------------------------- collide */
@@ -608,7 +740,8 @@ void or_reset_window(or_state *S)
 /* ----------------------------------------------------------- estimators */
 /* Per sampling cell (its n_sub collision cells summed in order), with K the
  * sampled steps in the window and N the particles:
- *   nu = S0 C / (K N)                     density over the mean density
+ *   nu = S0 C / (K N)                     density over the nominal density
+ *                                         (N = C ppc, the initial count)
  *   u_a = S1_a / S0, M_ab = S2_ab/S0 - u_a u_b, T = trace(M)/3
  *   P_xy = nu M_xy                        shear stress over n kT_ref
  *   P_xy,mid = nu ((S_xy + S_xy,pre)/2 / S0 - u_x u_y)
@@ -625,7 +758,7 @@ void or_estimators(const or_state *S, double *nu, double *ux, double *uy, double
 {
     const double v0 = sqrt(2.0);
     const int32_t C = S->C, ns = S->p.n_sub;
-    const double K = (double)S->n_sampled, N = (double)S->N;
+    const double K = (double)S->n_sampled, N = (double)S->Nnom;
     double qsum = 0.0;
     for (int32_t c = 0; c < C; ++c) {
         double s[NMOM];
@@ -662,6 +795,18 @@ void or_estimators(const or_state *S, double *nu, double *ux, double *uy, double
 
 /* --------------------------------------------------------------- access */
 int32_t or_n_particles(const or_state *S) { return S->N; }
+int32_t or_capacity(const or_state *S) { return S->Ncap; }
+
+/* open-boundary diagnostics: live particles, particles injected and removed
+ * since creation, status bits, the injection remainder */
+void or_open_diagnostics(const or_state *S, double out[5])
+{
+    out[0] = (double)S->N;
+    out[1] = (double)S->n_injected;
+    out[2] = (double)S->n_deleted;
+    out[3] = (double)S->status;
+    out[4] = S->inj_rem;
+}
 int32_t or_n_coll_cells(const or_state *S) { return S->Cc; }
 int64_t or_step_index(const or_state *S) { return S->step; }
 int64_t or_n_sampled(const or_state *S) { return S->n_sampled; }

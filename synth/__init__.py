@@ -45,6 +45,7 @@ class Params:
     seed: int = 0
     precision: int = FP64_DETERMINISTIC
     n_sub: int = 1
+    domain_length: float = 0.0   # 0: the closed gap; L > 0: wall at 0, open boundary at L
 
     @property
     def n_particles(self) -> int:
