@@ -90,6 +90,16 @@ typedef struct dsmc_params {
     uint32_t debug_phase_mask;  /* DSMC_PHASE_* subset for tests; 0 = all */
     int64_t n_transient;        /* steps before sampling starts, >= 0 */
     uint64_t seed;              /* key of every random stream */
+    double domain_length;       /* 0: the closed gap [0, H] between the two plates.
+                                   L in (0, H]: a patch of the hybrid (Sec. 2, Sec. 3.2):
+                                   the plate at y = 0 and an open boundary at y = L, the
+                                   n_cells cells spanning [0, L]; particles crossing L
+                                   outward are removed and particles enter through it from
+                                   the inflow set by dsmc_set_inflow (Chapman-Enskog,
+                                   default: at rest at T_w).  The particle count then
+                                   varies around n_cells * particles_per_cell; slots are
+                                   allocated for 25% more (at least 8 standard deviations
+                                   + 64).  Requires debug_phase_mask = 0. */
 } dsmc_params;
 
 /* Estimators over the current window (all arrays host, caller-owned, length
@@ -157,8 +167,9 @@ int dsmc_sync(dsmc_handle *h);
 int dsmc_destroy(dsmc_handle *h);
 
 /* Copy the particle state in slot order to host arrays of N elements (double
- * for the FP64 modes, float for FP32) and the steps completed.  Any pointer
- * may be NULL.  Synchronises. */
+ * for the FP64 modes, float for FP32; N = n_cells * particles_per_cell, or
+ * the n_live of dsmc_open_state for an open instance) and the steps
+ * completed.  Any pointer may be NULL.  Synchronises. */
 int dsmc_get_state(dsmc_handle *h, void *y, void *vx, void *vy, void *vz, int32_t *cell,
                    uint64_t *step);
 
@@ -167,6 +178,32 @@ int dsmc_get_state(dsmc_handle *h, void *y, void *vx, void *vy, void *vz, int32_
  * checkpoint exactly. */
 int dsmc_set_state(dsmc_handle *h, const void *y, const void *vx, const void *vy,
                    const void *vz, const int32_t *cell, uint64_t step);
+
+/* Inflow of an open instance (domain_length > 0) at its open boundary
+ * (Sec. 2: the hybrid imposes the Chapman-Enskog distribution at the local
+ * macro state there): mean x velocity u and its gradient du/dy in the units
+ * of Eq. 6, temperature over T_ref and density over the nominal density.
+ * Entering particles follow the flux-weighted distribution of pure shear,
+ * f_Maxwell (1 - a C_x C_y) with C = (c - u)/sqrt(2 k T/m) and
+ * a = (4 Kn/sqrt(pi)) du/dy / (n sqrt(T)) (Newton's law for hard spheres);
+ * floor(expected + carried remainder) enter per step, the expected number
+ * being the Maxwellian inward flux n sqrt(kT/(2 pi m)) dt times the nominal
+ * line density.  Applies to the steps enqueued after the call (it waits for
+ * the earlier ones).  INVALID_ARG if the instance is closed, any value is
+ * non-finite, T <= 0, n < 0, |a| > 1 (a stress beyond half the pressure,
+ * outside the expansion's range) or more particles would be expected per
+ * step than there are slots. */
+int dsmc_set_inflow(dsmc_handle *h, double u, double dudy, double temperature, double density);
+
+/* Open instance: particles in the domain after the last step, and particles
+ * injected and removed through the boundary since creation, and the carried
+ * fraction of the injections (any pointer may be NULL).  Synchronises.
+ * dsmc_get_state / dsmc_set_state of an open instance move n_live particles.
+ * INVALID_ARG if the instance is closed; NUMERIC if the slots ran out
+ * (an injection found no room; the allocation holds 25% over the nominal
+ * count). */
+int dsmc_open_state(dsmc_handle *h, int32_t *n_live, int64_t *n_injected, int64_t *n_removed,
+                    double *inj_remainder);
 
 /* Per collision cell (n_cells*n_sub each, host): crmax, the NTC remainder,
  * particle count and slot offset after the last sort.  NULL skips. */

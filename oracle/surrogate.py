@@ -78,13 +78,17 @@ def newton_error(u, P, dy, kn):
     return [P[i] + c * g[i] for i in range(len(u))]
 
 
-def constitutive_system(us, Ps, kn, k, b=None):
+def constitutive_system(us, Ps, kn, k, b=None, dy=None, n_train=None):
     """Target vector t_{i + j N_P} = E_{i,j} and design matrix of model C_k
-    (Appendix A) from samples us[j][i], Ps[j][i] on cells of width 1/N_P."""
-    n_p = len(us[0])
-    dy = 1.0 / n_p
+    (Appendix A) from samples us[j][i], Ps[j][i] on cells of width dy from
+    the bottom plate (default 1/len(us[j]): the whole gap).  n_train keeps
+    the first n_train cells only (a patch of the hybrid, whose last cells
+    are its buffer, Sec. 3.2); the gradient still uses every cell."""
+    n_c = len(us[0])
+    dy = 1.0 / n_c if dy is None else dy
+    n_p = n_c if n_train is None else n_train
     b = exponents(kn) if b is None else b
-    y = [(i + 0.5) * dy for i in range(n_p)]
+    y = [(i + 0.5) * dy for i in range(n_c)]
     t = []
     rows = []
     for j in range(len(us)):
@@ -106,18 +110,20 @@ def wall_velocities(u, wall="extrapolated"):
     return 1.5 * u[0] - 0.5 * u[1], 1.5 * u[n - 1] - 0.5 * u[n - 2]
 
 
-def slip_system(us, force, slip, wall="extrapolated"):
+def slip_system(us, force, slip, wall="extrapolated", plates=2):
     """Targets u_j(y_bot), u_j(y_top) and the slip model's design column
     -P(y_bot) = F, P(y_top) = F (Eq. 12 and Appendix A); the no-slip model
-    (Eq. 11) has no column."""
+    (Eq. 11) has no column.  plates = 1: the samples are patches at the
+    bottom plate only (u_j(y_bot) alone)."""
     t = []
     rows = []
     for u in us:
         ub, ut = wall_velocities(u, wall)
         t.append(ub)
-        t.append(ut)
         rows.append([force] if slip else [])
-        rows.append([force] if slip else [])
+        if plates == 2:
+            t.append(ut)
+            rows.append([force] if slip else [])
     return np.array(rows, dtype=np.float64).reshape(len(t), 1 if slip else 0), np.array(t, dtype=np.float64)
 
 

@@ -32,9 +32,28 @@ struct DevScalars {
     int64_t step_done;            // steps completed
     int64_t n_sampled;            // sampled steps in the window
     int32_t status;               // bit 0: non-finite velocity, bit 1: particle count lost,
-                                  // bit 2: a sorted slot out of range
+                                  // bit 2: a sorted slot out of range, bit 3: an
+                                  // injection needed more slots than allocated
     int32_t pad_[3];
 };
+
+// State of an open boundary (a patch with a wall at y = 0 and an open
+// boundary at its top, y = H of the descriptor).  The first six fields are
+// the inflow the host sets (dsmc_set_inflow); the rest the kernels keep.
+struct OpenState {
+    double u_in;          // mean x velocity of the inflow (sqrt(kT_ref/m) units)
+    double sqrt_tin;      // sqrt(T) of the inflow
+    double vt_in;         // its thermal speed sqrt(2 T)
+    double ce_a;          // Chapman-Enskog shear weight a of 1 - a C_x C_y
+    double ce_A;          // bound of the weight used by the acceptance test
+    double inj_expected;  // particles expected to enter per step
+    double inj_rem;       // carried fractional part of the injections
+    int64_t n_injected;   // particles injected since creation
+    int64_t n_deleted;    // particles removed through the boundary since creation
+    int32_t n_live;       // particles after the last sort (slots 0 .. n_live - 1)
+    int32_t n_used;       // slots holding particles during the current step
+};
+constexpr int kOpenInflowDoubles = 6;   // leading doubles of OpenState set by the host
 
 // Counters are kept per collision cell and written only by the wavefront
 // that owns the cell: a single device-wide counter updated by every
@@ -54,14 +73,19 @@ struct DevScalars {
 // finishes the sort by cell inside each bucket (writing count / offset).
 // Both orders end as the stable sort of the particles by cell.
 struct InstDesc {
-    int32_t N, C, Cc, n_sub;           // particles, sampling cells, collision cells, Cc / C
+    int32_t N, C, Cc, n_sub;           // nominal particles (C * ppc), sampling cells,
+                                       // collision cells, Cc / C
     int32_t tiles, tile_items, nseg, ppc;  // particle tiles, items per tile, scan segments
-    double H, dt, g, kntc, crmax0, sqrt_tw, inv_dy, pad0_;
+    double H, dt, g, kntc, crmax0, sqrt_tw, inv_dy, pad0_;  // H: top of the domain
     int64_t n_transient;
     uint32_t key0, key1;
     uint32_t phase_mask;
-    int32_t pad1_;
-    int32_t nkeys, key_shift;          // sort keys, log2 of cells per key
+    int32_t open;                      // 1: the top (y = H) is an open boundary
+    int32_t nkeys, key_shift;          // sort keys, log2 of cells per key; an open
+                                       // instance's last key gathers the particles
+                                       // that left, past every cell
+    int32_t ncap, pad2_;               // particle slots allocated (N when closed)
+    OpenState* os;                     // open instances: the boundary's state
     void* buf[2][4];
     int32_t* cell;     // N: sort key of each slot (pre-sort order)
     int32_t* counts;   // tiles * nkeys: per-tile histogram, then per-tile scatter bases

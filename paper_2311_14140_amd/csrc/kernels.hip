@@ -95,6 +95,77 @@ __global__ void k_init(const InstDesc* __restrict__ descs) {
         d.sc->step_done = 0;
         d.sc->n_sampled = 0;
         d.sc->status = 0;
+        if (d.open) {
+            d.os->inj_rem = 0.0;
+            d.os->n_injected = 0;
+            d.os->n_deleted = 0;
+            d.os->n_live = d.N;
+            d.os->n_used = d.N;
+        }
+    }
+}
+
+// ------------------------------------------------------------- injection
+// Particles entering an open instance through its top at the start of a step
+// (the hybrid's inflow: the Chapman-Enskog distribution of pure shear at the
+// macro state imposed there, Sec. 2): floor(expected + carried remainder) of
+// them, placed after the live slots of the step's source buffer.  Injection k
+// of step s draws from tag kTagInject, entity k.  Per attempt one call gives
+// the acceptance uniform and the flux-weighted inward speed sqrt(-2 T ln U),
+// a polar pair from the following calls the thermal x and z velocities, and
+// the attempt is kept with probability (1 - a C_x C_y) / A, C = c / sqrt(2T);
+// a last call gives the fraction of the step spent inside.  The particle
+// starts where a straight flight of the whole step brings it across the
+// boundary at that moment, with the force's x velocity gain of the outside
+// part taken off, so the ordinary move delivers it with the drawn velocity at
+// the boundary.  Drawn in FP64 for every precision, then stored.
+template <class R>
+__global__ __launch_bounds__(256) void k_inject(const InstDesc* __restrict__ descs) {
+    const InstDesc& d = descs[blockIdx.x];
+    if (!d.open) return;
+    __shared__ int sh_n, sh_live;
+    OpenState* os = d.os;
+    if (threadIdx.x == 0) {
+        const int live = os->n_live;
+        const double m = os->inj_expected + os->inj_rem;
+        const double f = floor(m);
+        os->inj_rem = m - f;
+        int64_t n = (int64_t)f;
+        if ((int64_t)live + n > (int64_t)d.ncap) {
+            atomicOr(&d.sc->status, 8);
+            n = (int64_t)d.ncap - (int64_t)live;
+        }
+        os->n_injected += n;
+        os->n_used = live + (int)n;
+        sh_n = (int)n;
+        sh_live = live;
+    }
+    __syncthreads();
+    const int n = sh_n, live = sh_live;
+    const int64_t s = d.sc->step_done + 1;
+    const P4<R> b = particles<R>(d, (int)((s - 1) & 1));
+    const double sqrt_tin = os->sqrt_tin, vt = os->vt_in, a = os->ce_a, A = os->ce_A;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        Stream st(d.key0, d.key1, (uint32_t)s, (uint32_t)k, 0u, kTagInject);
+        double sp, tx, tz;
+        for (;;) {
+            double ua, ub;
+            Num<double>::uni2(st.next(), ua, ub);
+            sp = __builtin_sqrt(-2.0 * series_log(ub)) * sqrt_tin;
+            normal_pair<double>(st, sqrt_tin, tx, tz);
+            const double cx = tx / vt;
+            const double cy = -sp / vt;
+            const double gam = 1.0 - a * (cx * cy);
+            if (ua * A < gam) break;
+        }
+        double ut, unused;
+        Num<double>::uni2(st.next(), ut, unused);
+        const double outside = d.dt - ut * d.dt;
+        const int q = live + k;
+        b.y[q] = (R)(d.H + sp * outside);
+        b.vx[q] = (R)((os->u_in + tx) - d.g * outside);
+        b.vy[q] = (R)(-sp);
+        b.vz[q] = (R)tz;
     }
 }
 
@@ -120,10 +191,12 @@ template <class R> __device__ __forceinline__ R time_to_wall(const InstDesc& d, 
 
 // The first segment: when no plate is reached within dt the particle flies
 // straight (returns true); otherwise the state is left as it is and the
-// plate (top or not) and the time left when it is reached are returned.
+// plate (top or not) and the time left when it is reached are returned.  In
+// an open instance the top is the open boundary: a particle reaching it
+// leaves the domain (returns true with gone set; its state is then void).
 template <class R>
 __device__ __forceinline__ bool flight_start(const InstDesc& d, R& y, R& vx, R vy, R& t_left,
-                                             bool& top) {
+                                             bool& top, bool& gone) {
     const R H = (R)d.H, g = (R)d.g, t = (R)d.dt;
     const R tw = time_to_wall<R>(d, y, vy);
     if (tw >= t) {
@@ -134,6 +207,10 @@ __device__ __forceinline__ bool flight_start(const InstDesc& d, R& y, R& vx, R v
         return true;
     }
     top = vy > R(0);
+    if (top && d.open) {
+        gone = true;
+        return true;
+    }
     t_left = t - tw;
     return false;
 }
@@ -144,7 +221,8 @@ __device__ __forceinline__ bool flight_start(const InstDesc& d, R& y, R& vx, R v
 // not read.  Returns the number of hits.
 template <class R>
 __device__ __forceinline__ int flight_from_wall(const InstDesc& d, uint32_t step, uint32_t slot,
-                                                bool top, R t, R& y, R& vx, R& vy, R& vz) {
+                                                bool top, R t, R& y, R& vx, R& vy, R& vz,
+                                                bool& gone) {
     const R H = (R)d.H, g = (R)d.g, sd = (R)d.sqrt_tw;
     int h = 0;
     for (;;) {
@@ -161,6 +239,10 @@ __device__ __forceinline__ int flight_from_wall(const InstDesc& d, uint32_t step
             break;
         }
         top = vy > R(0);
+        if (top && d.open) {
+            gone = true;
+            break;
+        }
         t = t - tw;
     }
     if (y < R(0)) y = R(0);
@@ -172,7 +254,7 @@ __device__ __forceinline__ int flight_from_wall(const InstDesc& d, uint32_t step
 // flight_start followed by flight_from_wall).  Returns the number of hits.
 template <class R>
 __device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32_t slot, R& y,
-                                        R& vx, R& vy, R& vz) {
+                                        R& vx, R& vy, R& vz, bool& gone) {
     const R H = (R)d.H, g = (R)d.g, sd = (R)d.sqrt_tw;
     R t = (R)d.dt;
     int h = 0;
@@ -184,6 +266,10 @@ __device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32
             break;
         }
         const bool top = vy > R(0);
+        if (top && d.open) {
+            gone = true;
+            break;
+        }
         y = top ? H : R(0);
         t = t - tw;
         Stream st(d.key0, d.key1, step, slot, (uint32_t)h, kTagWall);
@@ -202,6 +288,17 @@ template <class R> __device__ __forceinline__ int cell_of(const InstDesc& d, R y
     if (c >= d.Cc) c = d.Cc - 1;
     if (!(c >= 0)) c = 0;  // only reachable from a non-finite position
     return c;
+}
+
+// Sort key after a flight: the particle's cell's key, or, for a particle that
+// left through an open boundary, the instance's last key (past every cell).
+template <class R> __device__ __forceinline__ int key_of(const InstDesc& d, R y, bool gone) {
+    return gone ? d.nkeys - 1 : (cell_of<R>(d, y) >> d.key_shift);
+}
+
+// Slots holding particles during the current step.
+__device__ __forceinline__ int slots_used(const InstDesc& d) {
+    return d.open ? d.os->n_used : d.N;
 }
 
 template <class R, bool kMove>
@@ -225,7 +322,8 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* 
         int c;
         if (kMove) {
             R y = b.y[p], vx = b.vx[p], vy = b.vy[p], vz = b.vz[p];
-            const int h = move_one<R>(d, (uint32_t)s, (uint32_t)p, y, vx, vy, vz);
+            bool gone = false;  // debug paths run closed instances only
+            const int h = move_one<R>(d, (uint32_t)s, (uint32_t)p, y, vx, vy, vz, gone);
             b.y[p] = y;
             b.vx[p] = vx;
             if (h) {
@@ -326,9 +424,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
         int run = incl - local + (wv ? wsum[wv - 1] : 0);
         for (int c = c0; c < c1; ++c) {
             d.koffset[c] = run;
+            // an open instance's last key holds the particles that left: the
+            // live ones are those before it
+            if (d.open && c == Cc - 1) {
+                d.os->n_live = run;
+                d.os->n_deleted += d.kcount[c];
+            }
             run += d.kcount[c];
         }
-        if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != d.N) atomicOr(&d.sc->status, 2);
+        if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != slots_used(d))
+            atomicOr(&d.sc->status, 2);
     }
     __syncthreads();
     if (tid == 0) {
@@ -509,12 +614,14 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
 // full (the same arithmetic and draws, so the same key) and writes the moved
 // record straight to its sorted slot.
 
-// Flight of the position alone: the y that move_one would produce.
+// Flight of the position alone: the sort key of the y that move_one would
+// produce.
 template <class R>
-__device__ __forceinline__ R flight_y(const InstDesc& d, uint32_t step, uint32_t slot, R y, R vy) {
+__device__ __forceinline__ int flight_key(const InstDesc& d, uint32_t step, uint32_t slot, R y, R vy) {
     R vx = R(0), vz = R(0);
-    move_one<R>(d, step, slot, y, vx, vy, vz);
-    return y;
+    bool gone = false;
+    move_one<R>(d, step, slot, y, vx, vy, vz, gone);
+    return key_of<R>(d, y, gone);
 }
 
 template <class R>
@@ -529,7 +636,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __re
     const int64_t s = d.sc->step_done + 1;
     const P4<R> b = particles<R>(d, (int)((s - 1) & 1));
     const int start = w.y * d.tile_items;
-    const int end = min(start + d.tile_items, d.N);
+    const int end = min(start + d.tile_items, slots_used(d));
     constexpr int U = 4;
     for (int p0 = start + (int)threadIdx.x; p0 < end; p0 += U * kParticleThreads) {
         R y[U], vy[U];
@@ -545,10 +652,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __re
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = p0 + u * kParticleThreads;
-            if (p < end) {
-                const R yn = flight_y<R>(d, (uint32_t)s, (uint32_t)p, y[u], vy[u]);
-                atomicAdd(&hist[cell_of<R>(d, yn) >> d.key_shift], 1);
-            }
+            if (p < end) atomicAdd(&hist[flight_key<R>(d, (uint32_t)s, (uint32_t)p, y[u], vy[u])], 1);
         }
     }
     __syncthreads();
@@ -579,13 +683,13 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
     __shared__ int blk_bad;
     const int2 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
-    const int nk = d.nkeys, shift = d.key_shift;
+    const int nk = d.nkeys;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t s = d.sc->step_done;
     const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
     const P4<R> dst = particles<R>(d, (int)(s & 1));
     const int start = w.y * d.tile_items;
-    const int end = min(start + d.tile_items, d.N);
+    const int end = min(start + d.tile_items, slots_used(d));
     const bool staged = d.tile_items <= stage_max;
     int* delta = tables + kScatterWaves * nk;
     int* stage_pos = delta + nk;
@@ -629,14 +733,15 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
         R* qv = qx + qcap;
         R* qz = qv + qcap;
         int nq = 0, jq[K];
-        unsigned hitm = 0;
+        unsigned hitm = 0, gonem = 0;  // queued records; records that left the domain
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = q0 + 64 * k + lane;
-            bool hit = false, top = false;
+            bool hit = false, top = false, gone = false;
             R tl = R(0);
             jq[k] = 0;
-            if (i < q1) hit = !flight_start<R>(d, ry[k], rx[k], rv[k], tl, top);
+            if (i < q1) hit = !flight_start<R>(d, ry[k], rx[k], rv[k], tl, top, gone);
+            if (gone) gonem |= 1u << k;
             const unsigned long long hm = __ballot(hit);
             if (hit) {
                 const int j = nq + __popcll(hm & lanes_below(lane));
@@ -646,7 +751,10 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
                     jq[k] = j;
                     hitm |= 1u << k;
                 } else {
-                    flight_from_wall<R>(d, (uint32_t)s, (uint32_t)i, top, tl, ry[k], rx[k], rv[k], rz[k]);
+                    bool gone2 = false;
+                    flight_from_wall<R>(d, (uint32_t)s, (uint32_t)i, top, tl, ry[k], rx[k], rv[k], rz[k],
+                                        gone2);
+                    if (gone2) gonem |= 1u << k;
                 }
             }
             nq += __popcll(hm);
@@ -659,9 +767,10 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
             if (j < nproc) {
                 const R tt = qt[j];
                 R y = R(0), vx = R(0), vy = R(0), vz = R(0);
+                bool gone3 = false;
                 flight_from_wall<R>(d, (uint32_t)s, (uint32_t)qslot[j], tt > R(0), tt > R(0) ? tt : -tt,
-                                    y, vx, vy, vz);
-                qy[j] = y;
+                                    y, vx, vy, vz, gone3);
+                qy[j] = gone3 ? R(-1) : y;  // a flight ends at y >= 0: -1 marks one that left
                 qx[j] = vx;
                 qv[j] = vy;
                 qz[j] = vz;
@@ -679,18 +788,17 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
                 rx[k] = qx[j];
                 rv[k] = qv[j];
                 rz[k] = qz[j];
+                if (ry[k] < R(0)) gonem |= 1u << k;
             }
             if (i < q1) {
                 bad |= !(isfinite(rx[k]) && isfinite(rv[k]) && isfinite(rz[k]));
-                key[k] = cell_of<R>(d, ry[k]) >> shift;
+                key[k] = key_of<R>(d, ry[k], (gonem >> k) & 1u);
                 atomicAdd(&mine[key[k]], 1);
             }
         }
     } else {
-        for (int i = q0 + lane; i < q1; i += 64) {
-            const R yn = flight_y<R>(d, (uint32_t)s, (uint32_t)i, src.y[i], src.vy[i]);
-            atomicAdd(&mine[cell_of<R>(d, yn) >> shift], 1);
-        }
+        for (int i = q0 + lane; i < q1; i += 64)
+            atomicAdd(&mine[flight_key<R>(d, (uint32_t)s, (uint32_t)i, src.y[i], src.vy[i])], 1);
     }
     __syncthreads();
     for (int c = threadIdx.x; c < nk; c += blockDim.x) {
@@ -749,9 +857,9 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
                 stage_rec[2 * stage_max + l] = vy;
                 stage_rec[3 * stage_max + l] = vz;
             } else {
-                if (pos < 0 || pos >= d.N) {
+                if (pos < 0 || pos >= d.ncap) {
                     bad |= 2;
-                    pos = pos < 0 ? 0 : d.N - 1;
+                    pos = pos < 0 ? 0 : d.ncap - 1;
                 }
                 dst.y[pos] = y;
                 dst.vx[pos] = vx;
@@ -777,9 +885,10 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
                 vx = src.vx[i];
                 vy = src.vy[i];
                 vz = src.vz[i];
-                move_one<R>(d, (uint32_t)s, (uint32_t)i, y, vx, vy, vz);
+                bool gone = false;
+                move_one<R>(d, (uint32_t)s, (uint32_t)i, y, vx, vy, vz, gone);
                 bad |= !(isfinite(vx) && isfinite(vy) && isfinite(vz));
-                kk = cell_of<R>(d, y) >> shift;
+                kk = key_of<R>(d, y, gone);
             }
             place(valid, kk, y, vx, vy, vz);
         }
@@ -789,7 +898,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
     if (staged) {
         for (int l = threadIdx.x; l < n_tile; l += blockDim.x) {
             int pos = stage_pos[l];
-            if (pos < 0 || pos >= d.N) pos = pos < 0 ? 0 : d.N - 1;  // flagged above
+            if (pos < 0 || pos >= d.ncap) pos = pos < 0 ? 0 : d.ncap - 1;  // flagged above
             dst.y[pos] = stage_rec[l];
             dst.vx[pos] = stage_rec[stage_max + l];
             dst.vy[pos] = stage_rec[2 * stage_max + l];
@@ -1756,6 +1865,8 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
     };
     mark(0);
     if ((phase & kPhaseMove) && (phase & kPhaseSort)) {
+        if (w.has_open)
+            hipLaunchKernelGGL((k_inject<R>), dim3(w.n_inst), dim3(256), 0, st, w.desc);
         hipLaunchKernelGGL((k_count<R>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds, st, w.desc,
                            w.tiles);
         mark(1);

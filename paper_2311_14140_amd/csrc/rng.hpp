@@ -17,7 +17,7 @@
 
 namespace dsmc {
 
-enum : uint32_t { kTagInit = 1u, kTagWall = 2u, kTagColl = 3u, kTagRound = 4u };
+enum : uint32_t { kTagInit = 1u, kTagWall = 2u, kTagColl = 3u, kTagInject = 5u };
 
 __host__ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll

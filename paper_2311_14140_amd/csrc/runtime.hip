@@ -50,12 +50,14 @@ struct Plan {
     int mode = 0;
     size_t rb = 8;  // bytes per real
     int32_t N = 0, C = 0, Cc = 0, ns = 1, ppc = 0;
+    int32_t ncap = 0;     // particle slots (N unless open)
+    int open = 0;         // 1: a patch with an open boundary at L
     int32_t tile_items = 256, tiles = 1, nseg = 1;
-    double H = 1.0, lam = 0, dt = 0, g = 0, kntc = 0, crmax0 = 0, sqrt_tw = 1, inv_dy = 0;
+    double H = 1.0, L = 1.0, lam = 0, dt = 0, g = 0, kntc = 0, crmax0 = 0, sqrt_tw = 1, inv_dy = 0;
     // arena offsets
     uint64_t off_buf[2][4], off_cell, off_counts, off_segsum, off_kcount, off_koffset, off_count,
         off_offset, off_crmax,
-        off_rem, off_acc, off_ncoll, off_est, off_sc, off_desc, total;
+        off_rem, off_acc, off_ncoll, off_est, off_sc, off_os, off_desc, total;
 };
 
 // Slots of a particle tile the scatter can lay out in LDS before writing: the
@@ -108,8 +110,23 @@ int check_params(const dsmc_params* p, std::string* err) {
         return fail(err, DSMC_ERR_INVALID_ARG, "n_cells * n_sub exceeds the collision-cell limit");
     if (p->n_transient < 0) return fail(err, DSMC_ERR_INVALID_ARG, "n_transient must be >= 0");
     if (p->debug_phase_mask > DSMC_PHASE_ALL) return fail(err, DSMC_ERR_INVALID_ARG, "bad phase mask");
+    if (!(std::isfinite(p->domain_length) && p->domain_length >= 0.0 && p->domain_length <= 1.0))
+        return fail(err, DSMC_ERR_INVALID_ARG, "domain_length must be in [0, 1]");
+    if (p->domain_length > 0.0 && p->debug_phase_mask != 0)
+        return fail(err, DSMC_ERR_INVALID_ARG, "an open domain runs whole steps only");
     return DSMC_OK;
 }
+
+constexpr double kPi = 0x1.921fb54442d18p+1;  // pi, correctly rounded
+
+}  // namespace
+
+struct dsmc_handle;
+namespace {
+void inflow_constants(const dsmc_handle* h, double u, double dudy, double T, double n, double out[6]);
+}  // namespace
+
+namespace {
 
 Plan make_plan(const dsmc_params* p) {
     Plan q;
@@ -120,6 +137,14 @@ Plan make_plan(const dsmc_params* p) {
     q.Cc = p->n_cells * p->n_sub;
     q.ppc = p->particles_per_cell;
     q.N = p->n_cells * p->particles_per_cell;
+    q.open = p->domain_length > 0.0;
+    q.ncap = q.N;
+    if (q.open) {
+        // the count of an open patch fluctuates about N: room for 25% more,
+        // and at least 8 standard deviations plus 64
+        const int64_t m1 = (int64_t)q.N / 4, m2 = (int64_t)(8.0 * std::sqrt((double)q.N)) + 64;
+        q.ncap = (int32_t)std::min<int64_t>((int64_t)q.N + std::max(m1, m2), (int64_t)INT32_MAX / 2);
+    }
     q.H = 1.0;
     q.lam = p->kn * q.H;
     if (p->dt > 0.0) {
@@ -132,7 +157,8 @@ Plan make_plan(const dsmc_params* p) {
     q.kntc = (q.dt * (double)p->n_sub) / ((std::sqrt(2.0) * q.lam) * (double)p->particles_per_cell);
     q.crmax0 = 5.0 * std::sqrt(2.0 * p->wall_temperature);
     q.sqrt_tw = std::sqrt(p->wall_temperature);
-    q.inv_dy = (double)q.Cc / q.H;
+    q.L = q.open ? p->domain_length : q.H;
+    q.inv_dy = (double)q.Cc / q.L;
     int k = base_items_per_thread(q.N, q.Cc, q.rb);
     if (bucket_eligible(p)) {
         // few sort keys: tiles as large as the move-scatter holds in registers
@@ -140,7 +166,7 @@ Plan make_plan(const dsmc_params* p) {
         k = std::max(1, std::min(regs, (q.N + kParticleThreads - 1) / kParticleThreads));
     }
     q.tile_items = k * kParticleThreads;
-    q.tiles = (q.N + q.tile_items - 1) / q.tile_items;
+    q.tiles = (q.ncap + q.tile_items - 1) / q.tile_items;
     q.nseg = (q.tiles + kSegTiles - 1) / kSegTiles;
 
     uint64_t o = 0;
@@ -149,21 +175,24 @@ Plan make_plan(const dsmc_params* p) {
         o = align_up(o + bytes);
         return at;
     };
+    // an open instance's sort has one key more (the particles that left)
+    const uint64_t keys = (uint64_t)q.Cc + (uint64_t)q.open;
     for (int b = 0; b < 2; ++b)
-        for (int a = 0; a < 4; ++a) q.off_buf[b][a] = take((uint64_t)q.N * q.rb);
-    q.off_cell = take((uint64_t)q.N * 4);
-    q.off_counts = take((uint64_t)q.tiles * q.Cc * 4);
-    q.off_segsum = take((uint64_t)q.nseg * q.Cc * 4);
-    q.off_kcount = take((uint64_t)q.Cc * 4);
-    q.off_koffset = take((uint64_t)q.Cc * 4);
-    q.off_count = take((uint64_t)q.Cc * 4);
-    q.off_offset = take((uint64_t)q.Cc * 4);
+        for (int a = 0; a < 4; ++a) q.off_buf[b][a] = take((uint64_t)q.ncap * q.rb);
+    q.off_cell = take((uint64_t)q.ncap * 4);
+    q.off_counts = take((uint64_t)q.tiles * keys * 4);
+    q.off_segsum = take((uint64_t)q.nseg * keys * 4);
+    q.off_kcount = take(keys * 4);
+    q.off_koffset = take(keys * 4);
+    q.off_count = take(keys * 4);
+    q.off_offset = take(keys * 4);
     q.off_crmax = take((uint64_t)q.Cc * 8);
     q.off_rem = take((uint64_t)q.Cc * 8);
     q.off_acc = take((uint64_t)q.Cc * kMoments * 8);
     q.off_ncoll = take((uint64_t)q.Cc * 4);
     q.off_est = take(((uint64_t)kEstPerCell * q.C + 3) * 8);
     q.off_sc = take(sizeof(DevScalars));
+    q.off_os = take(sizeof(OpenState));
     q.off_desc = take(sizeof(InstDesc));
     q.total = o + kAlign;  // slack to align an unaligned arena
     return q;
@@ -220,8 +249,28 @@ struct dsmc_handle {
     bool sorted = false;
     int32_t* bucket_count = nullptr;   // per-bucket count / offset (bucket-sorted launch shapes)
     int32_t* bucket_offset = nullptr;
+    double inflow[kOpenInflowDoubles] = {0, 0, 0, 0, 0, 0};  // source of the inflow copies
     std::string err;
 };
+
+namespace {
+// Inflow constants of an open instance (the OpenState fields the host sets),
+// each evaluated once in double in the order written: mean x velocity in
+// sqrt(kT_ref/m) units, sqrt(T), sqrt(2T), the Chapman-Enskog shear weight
+// a = (4 Kn/sqrt(pi)) du/dy / (n sqrt(T)) of the factor 1 - a C_x C_y, its
+// acceptance bound 1 + 16 |a|, and the particles expected to enter per step,
+// n (N / L) sqrt(T / (2 pi)) dt (the Maxwellian inward flux; the shear term
+// carries no net number flux).
+void inflow_constants(const dsmc_handle* h, double u, double dudy, double T, double n, double out[6]) {
+    const Plan& q = h->plan;
+    out[0] = u * std::sqrt(2.0);
+    out[1] = std::sqrt(T);
+    out[2] = std::sqrt(2.0 * T);
+    out[3] = (((4.0 * h->p.kn) / std::sqrt(kPi)) * dudy) / (n * out[1]);
+    out[4] = 1.0 + 16.0 * std::fabs(out[3]);
+    out[5] = ((n * ((double)q.N / q.L)) * std::sqrt(T / (2.0 * kPi))) * q.dt;
+}
+}  // namespace
 
 // A lane of a group: a subset of its members with their own work lists, step
 // graph and stream.  The lanes of a group run concurrently; each step forks
@@ -365,6 +414,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
     std::vector<int4> cols, cblocks, gblocks;
     int max_cc = 1;
     int cap = 64, group_cap = 64;
+    int has_open = 0;
     for (int i = 0; i < n; ++i) {
         dsmc_handle* h = lane.members[i];
         InstDesc d = h->desc;
@@ -379,22 +429,23 @@ int build_lane(dsmc_group* g, Lane& lane) {
         if (bucketed) {
             const int target = g->ppb > 0 ? g->ppb : (g->mode == kFp32Fast ? 2048 : 1024);
             d.key_shift = bucket_shift(per_cell, target);
-            d.nkeys = (d.Cc + (1 << d.key_shift) - 1) >> d.key_shift;
+            d.nkeys = ((d.Cc + (1 << d.key_shift) - 1) >> d.key_shift) + d.open;
             d.kcount = h->bucket_count;
             d.koffset = h->bucket_offset;
         } else {
             d.key_shift = 0;
-            d.nkeys = d.Cc;
+            d.nkeys = d.Cc + d.open;
             d.kcount = d.count;
             d.koffset = d.offset;
         }
+        has_open |= d.open;
         // launch shape: tiles may only grow (the histogram matrix is sized
         // for the base tile and all cells)
         const int mult = g->tile_mult > 0 ? g->tile_mult : 1;
         const int64_t items = std::min<int64_t>(base_items * mult,
-                                                (int64_t)std::max(h->plan.N, 1) + kParticleThreads);
+                                                (int64_t)std::max(h->plan.ncap, 1) + kParticleThreads);
         d.tile_items = (int32_t)((items + kParticleThreads - 1) / kParticleThreads * kParticleThreads);
-        d.tiles = (d.N + d.tile_items - 1) / d.tile_items;
+        d.tiles = (d.ncap + d.tile_items - 1) / d.tile_items;
         d.nseg = (d.tiles + kSegTiles - 1) / kSegTiles;
         descs[i] = d;
         for (int t = 0; t < d.tiles; ++t) tiles.push_back(make_int2(i, t));
@@ -409,7 +460,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
             // raised so that a bucket's cells occupy the workgroup's lanes
             const int cpk = 1 << d.key_shift;
             const int G = std::min(64, std::max(group_width(per_cell), kFastWaves * 64 / cpk));
-            for (int b = 0; b < d.nkeys; ++b) gblocks.push_back(make_int4(i, b, G, 0));
+            for (int b = 0; b < d.nkeys - d.open; ++b) gblocks.push_back(make_int4(i, b, G, 0));
             const double per_block = per_cell * cpk;
             group_cap = std::max(group_cap, (int)std::ceil(per_block + 4.0 * std::sqrt(per_block) + 32.0));
         } else {
@@ -484,6 +535,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
     w.max_cc = max_cc;
     w.stage_max = stage_max;
     w.fast_cap = cap;
+    w.has_open = has_open;
     return DSMC_OK;
 }
 
@@ -576,6 +628,19 @@ int sync_check(dsmc_handle* h) {
     if (sc.status & 1) return fail(&h->err, DSMC_ERR_NUMERIC, "non-finite particle velocity");
     if (sc.status & 2) return fail(&h->err, DSMC_ERR_NUMERIC, "cell counts do not add up to N");
     if (sc.status & 4) return fail(&h->err, DSMC_ERR_NUMERIC, "sorted slot out of range");
+    if (sc.status & 8) return fail(&h->err, DSMC_ERR_NUMERIC, "open boundary: particle slots exhausted");
+    return DSMC_OK;
+}
+
+// Particles in the handle's slots after the last sort (the nominal count
+// unless the instance is open).  Synchronises.
+int live_count(dsmc_handle* h, int32_t* n) {
+    *n = h->plan.N;
+    if (!h->plan.open) return DSMC_OK;
+    HIP_TRY(&h->err, hipStreamSynchronize(stream_of(h)));
+    OpenState os;
+    HIP_TRY(&h->err, hipMemcpy(&os, h->desc.os, sizeof os, hipMemcpyDeviceToHost));
+    *n = os.n_live;
     return DSMC_OK;
 }
 
@@ -727,7 +792,10 @@ int dsmc_create(const dsmc_params* p, void* stream, void* arena, uint64_t arena_
     d.tile_items = q.tile_items;
     d.nseg = q.nseg;
     d.ppc = q.ppc;
-    d.H = q.H;
+    d.H = q.L;  // top of the domain: the far plate, or the patch's open boundary
+    d.open = q.open;
+    d.ncap = q.ncap;
+    d.os = q.open ? (OpenState*)(base + q.off_os) : nullptr;
     d.dt = q.dt;
     d.g = q.g;
     d.kntc = q.kntc;
@@ -745,8 +813,10 @@ int dsmc_create(const dsmc_params* p, void* stream, void* arena, uint64_t arena_
     d.segsum = (int32_t*)(base + q.off_segsum);
     d.count = (int32_t*)(base + q.off_count);
     d.offset = (int32_t*)(base + q.off_offset);
-    // sorted by cell unless a group's launch shape sorts it by buckets
-    d.nkeys = q.Cc;
+    // sorted by cell unless a group's launch shape sorts it by buckets (an
+    // open instance has one key more, past every cell, for the particles
+    // that left)
+    d.nkeys = q.Cc + q.open;
     d.key_shift = 0;
     d.kcount = d.count;
     d.koffset = d.offset;
@@ -762,6 +832,11 @@ int dsmc_create(const dsmc_params* p, void* stream, void* arena, uint64_t arena_
     device_max_lds();
     const char* where = "copy of the instance descriptor";
     hipError_t e = hipMemcpyAsync(h->d_desc, &h->desc, sizeof(InstDesc), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess && q.open) {
+        where = "copy of the inflow";
+        inflow_constants(h, 0.0, 0.0, p->wall_temperature, 1.0, h->inflow);
+        e = hipMemcpyAsync(d.os, h->inflow, sizeof(h->inflow), hipMemcpyHostToDevice, h->stream);
+    }
     if (e == hipSuccess) {
         where = "init kernel launch";
         launch_init(h->desc, h->d_desc, (Mode)q.mode, h->stream);
@@ -847,8 +922,11 @@ int dsmc_get_state(dsmc_handle* h, void* y, void* vx, void* vy, void* vz, int32_
     if (r) return r;
     DevScalars sc;
     HIP_TRY(&h->err, hipMemcpy(&sc, h->desc.sc, sizeof sc, hipMemcpyDeviceToHost));
+    int32_t n_live = 0;
+    r = live_count(h, &n_live);
+    if (r) return r;
     const int b = (int)(sc.step_done & 1);
-    const size_t bytes = (size_t)h->plan.N * h->plan.rb;
+    const size_t bytes = (size_t)n_live * h->plan.rb;
     void* outs[4] = {y, vx, vy, vz};
     for (int a = 0; a < 4; ++a)
         if (outs[a]) HIP_TRY(&h->err, hipMemcpy(outs[a], h->desc.buf[b][a], bytes, hipMemcpyDeviceToHost));
@@ -861,7 +939,7 @@ int dsmc_get_state(dsmc_handle* h, void* y, void* vx, void* vy, void* vz, int32_
             for (size_t k = 0; k < c; ++k)
                 for (int32_t i = 0; i < count[k]; ++i) cell[offset[k] + i] = (int32_t)k;
         } else {
-            HIP_TRY(&h->err, hipMemcpy(cell, h->desc.cell, (size_t)h->plan.N * 4, hipMemcpyDeviceToHost));
+            HIP_TRY(&h->err, hipMemcpy(cell, h->desc.cell, (size_t)n_live * 4, hipMemcpyDeviceToHost));
         }
     }
     if (step) *step = (uint64_t)sc.step_done;
@@ -878,7 +956,10 @@ int dsmc_set_state(dsmc_handle* h, const void* y, const void* vx, const void* vy
     const int b_old = (int)(sc.step_done & 1);
     sc.step_done = (int64_t)step;
     const int b = (int)(step & 1);
-    const size_t bytes = (size_t)h->plan.N * h->plan.rb;
+    int32_t n_live = 0;
+    r = live_count(h, &n_live);
+    if (r) return r;
+    const size_t bytes = (size_t)n_live * h->plan.rb;
     const void* ins[4] = {y, vx, vy, vz};
     for (int a = 0; a < 4; ++a) {
         if (ins[a]) {
@@ -888,9 +969,49 @@ int dsmc_set_state(dsmc_handle* h, const void* y, const void* vx, const void* vy
             HIP_TRY(&h->err, hipMemcpy(h->desc.buf[b][a], h->desc.buf[b_old][a], bytes, hipMemcpyDeviceToDevice));
         }
     }
-    if (cell) HIP_TRY(&h->err, hipMemcpy(h->desc.cell, cell, (size_t)h->plan.N * 4, hipMemcpyHostToDevice));
+    if (cell) HIP_TRY(&h->err, hipMemcpy(h->desc.cell, cell, (size_t)n_live * 4, hipMemcpyHostToDevice));
     HIP_TRY(&h->err, hipMemcpy(h->desc.sc, &sc, sizeof sc, hipMemcpyHostToDevice));
     h->sorted = false;
+    return DSMC_OK;
+}
+
+int dsmc_set_inflow(dsmc_handle* h, double u, double dudy, double temperature, double density) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    if (!h->plan.open) return fail(&h->err, DSMC_ERR_INVALID_ARG, "the instance has no open boundary");
+    if (!(std::isfinite(u) && std::isfinite(dudy) && std::isfinite(temperature) && temperature > 0.0 &&
+          std::isfinite(density) && density >= 0.0))
+        return fail(&h->err, DSMC_ERR_INVALID_ARG, "inflow must be finite, T > 0, n >= 0");
+    double c[kOpenInflowDoubles];
+    inflow_constants(h, u, dudy, temperature, density, c);
+    // |a| <= 1 keeps the acceptance rate of the inflow draws above 1/17 (and
+    // the expansion within its range: |P_xy| <= P/2); the expected entrants
+    // of a step must fit the slots
+    if (density > 0.0 && !(std::fabs(c[3]) <= 1.0))
+        return fail(&h->err, DSMC_ERR_INVALID_ARG,
+                    "velocity gradient too large for the Chapman-Enskog inflow (|a| > 1)");
+    if (!(c[5] <= (double)h->plan.ncap))
+        return fail(&h->err, DSMC_ERR_INVALID_ARG, "inflow density too large for the particle slots");
+    // the copy is ordered on the instance's stream: steps enqueued before it
+    // use the previous inflow; its source stays with the handle
+    HIP_TRY(&h->err, hipStreamSynchronize(stream_of(h)));
+    std::memcpy(h->inflow, c, sizeof c);
+    HIP_TRY(&h->err, hipMemcpyAsync(h->desc.os, h->inflow, sizeof(h->inflow), hipMemcpyHostToDevice,
+                                    stream_of(h)));
+    return DSMC_OK;
+}
+
+int dsmc_open_state(dsmc_handle* h, int32_t* n_live, int64_t* n_injected, int64_t* n_removed,
+                    double* inj_remainder) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    if (!h->plan.open) return fail(&h->err, DSMC_ERR_INVALID_ARG, "the instance has no open boundary");
+    const int r = sync_check(h);
+    if (r) return r;
+    OpenState os;
+    HIP_TRY(&h->err, hipMemcpy(&os, h->desc.os, sizeof os, hipMemcpyDeviceToHost));
+    if (n_live) *n_live = os.n_live;
+    if (n_injected) *n_injected = os.n_injected;
+    if (n_removed) *n_removed = os.n_deleted;
+    if (inj_remainder) *inj_remainder = os.inj_rem;
     return DSMC_OK;
 }
 

@@ -36,7 +36,8 @@ EXPORTS = (
     "dsmc_set_cells", "dsmc_info", "dsmc_status_string", "dsmc_last_error",
     "dsmc_group_create", "dsmc_group_add", "dsmc_group_remove", "dsmc_group_step",
     "dsmc_group_sync", "dsmc_group_size", "dsmc_group_lanes", "dsmc_group_destroy", "dsmc_group_set_tuning",
-    "dsmc_group_autotune", "dsmc_profile_step", "dsmc_group_sample",
+    "dsmc_group_autotune", "dsmc_profile_step", "dsmc_group_sample", "dsmc_set_inflow",
+    "dsmc_open_state",
 )
 
 
@@ -52,7 +53,7 @@ class dsmc_params(ct.Structure):
                 ("dt", ct.c_double), ("n_cells", ct.c_int32),
                 ("particles_per_cell", ct.c_int32), ("n_sub", ct.c_int32),
                 ("debug_phase_mask", ct.c_uint32), ("n_transient", ct.c_int64),
-                ("seed", ct.c_uint64)]
+                ("seed", ct.c_uint64), ("domain_length", ct.c_double)]
 
 
 _dp = ct.POINTER(ct.c_double)
@@ -93,6 +94,9 @@ def _load():
         "dsmc_group_size": [vp, ct.POINTER(i32)],
         "dsmc_group_lanes": [vp, ct.POINTER(i32)],
         "dsmc_group_sample": [vp, vp, i32, ct.c_int],
+        "dsmc_set_inflow": [vp, ct.c_double, ct.c_double, ct.c_double, ct.c_double],
+        "dsmc_open_state": [vp, ct.POINTER(i32), ct.POINTER(i64), ct.POINTER(i64),
+                            ct.POINTER(ct.c_double)],
         "dsmc_group_destroy": [vp],
         "dsmc_group_set_tuning": [vp, i32, i32],
         "dsmc_group_autotune": [vp, ct.POINTER(i32), ct.POINTER(i32)],
@@ -137,6 +141,7 @@ def make_params(p) -> dsmc_params:
     c.debug_phase_mask = int(getattr(p, "debug_phase_mask", 0))
     c.n_transient = int(p.n_transient)
     c.seed = int(p.seed)
+    c.domain_length = float(getattr(p, "domain_length", 0.0))
     return c
 
 
@@ -184,6 +189,7 @@ class Solver:
         consts = np.zeros(6)
         _check(lib.dsmc_info(h, ct.byref(n), ct.byref(cc), _ptr(consts)), h)
         self.N, self.Cc, self.C = n.value, cc.value, int(params.n_cells)
+        self.open = float(getattr(params, "domain_length", 0.0)) > 0.0
         self.constants = dict(dt=consts[0], g=consts[1], kntc=consts[2], crmax0=consts[3],
                               inv_dy=consts[4], lam=consts[5])
         self.real = np.float32 if self.precision == DSMC_FP32_FAST else np.float64
@@ -250,8 +256,23 @@ class Solver:
         d["wall"] = float(out[7])
         return d
 
+    def set_inflow(self, u: float = 0.0, dudy: float = 0.0, T: float = 1.0, n: float = 1.0):
+        """Chapman-Enskog inflow at the open boundary of an open instance."""
+        _check(lib.dsmc_set_inflow(self._h, float(u), float(dudy), float(T), float(n)), self._h)
+
+    def open_state(self) -> dict:
+        """Live particles, injected and removed totals and the carried
+        injection remainder of an open instance."""
+        n, a, b, r = ct.c_int32(), ct.c_int64(), ct.c_int64(), ct.c_double()
+        _check(lib.dsmc_open_state(self._h, ct.byref(n), ct.byref(a), ct.byref(b), ct.byref(r)),
+               self._h)
+        return dict(n_live=n.value, n_injected=a.value, n_deleted=b.value, inj_rem=r.value)
+
+    def live(self) -> int:
+        return self.open_state()["n_live"] if self.open else self.N
+
     def get_state(self):
-        n = self.N
+        n = self.live()
         y, vx, vy, vz = (np.zeros(n, dtype=self.real) for _ in range(4))
         cell = np.zeros(n, dtype=np.int32)
         step = ct.c_uint64()
@@ -261,12 +282,13 @@ class Solver:
 
     def set_state(self, y=None, vx=None, vy=None, vz=None, cell=None, step: int = 0):
         keep = []
+        n_live = self.live()
 
         def conv(a, dt):
             if a is None:
                 return None
             a = np.ascontiguousarray(a, dtype=dt)
-            if a.shape != (self.N,):
+            if a.shape != (n_live,):
                 raise ValueError("state arrays must have N elements")
             keep.append(a)
             return _ptr(a)

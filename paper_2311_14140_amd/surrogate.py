@@ -179,13 +179,22 @@ class SurrogateTrainer:
     index array or boolean mask) restricts the constitutive targets to a set
     of cells, the gradient still being taken over the whole profile.
     ``wall`` picks the wall velocity of the boundary models:
-    ``"extrapolated"`` (to the plate) or ``"cell"`` (the nearest cell)."""
+    ``"extrapolated"`` (to the plate) or ``"cell"`` (the nearest cell).
+
+    For a patch of the hybrid (Sec. 3.2) the profiles cover only the cells
+    next to the bottom plate: ``dy`` is their width (default 1/n_cells, the
+    whole gap), ``cells`` the training cells (the patch without its buffer)
+    and ``plates=1`` takes the wall velocity of the bottom plate alone."""
 
     def __init__(self, kn: float, force: float, n_cells: int, exponents=None,
-                 max_order: int = MAX_ORDER, cells=None, wall: str = "extrapolated"):
+                 max_order: int = MAX_ORDER, cells=None, wall: str = "extrapolated",
+                 dy: float | None = None, plates: int = 2):
         if wall not in ("extrapolated", "cell"):
             raise ValueError("wall must be 'extrapolated' or 'cell'")
+        if plates not in (1, 2):
+            raise ValueError("plates must be 1 or 2")
         self.wall = wall
+        self.plates = plates
         if n_cells < 3:
             raise ValueError("the gradient needs at least three cells")
         if not 0 <= max_order <= MAX_ORDER:
@@ -193,7 +202,7 @@ class SurrogateTrainer:
         self.kn, self.force, self.n_cells = float(kn), float(force), int(n_cells)
         self.exponents = tuple(exponents) if exponents is not None else table_exponents(kn)
         self.max_order = max_order
-        self.dy = 1.0 / n_cells
+        self.dy = 1.0 / n_cells if dy is None else float(dy)
         self.y = (np.arange(n_cells) + 0.5) * self.dy
         self.visc = 2.0 * self.kn / math.sqrt(math.pi)
         sel = np.arange(n_cells) if cells is None else np.arange(n_cells)[cells]
@@ -238,10 +247,15 @@ class SurrogateTrainer:
         else:
             u_bot = 1.5 * ux[:, 0] - 0.5 * ux[:, 1]
             u_top = 1.5 * ux[:, -1] - 0.5 * ux[:, -2]
-        self._xx += S * (x_bot * x_bot + x_top * x_top)
-        self._xu += x_bot * float(u_bot.sum()) + x_top * float(u_top.sum())
-        self._uu += float(u_bot @ u_bot + u_top @ u_top)
-        self._usum += float(u_bot.sum() + u_top.sum())
+        self._xx += S * x_bot * x_bot
+        self._xu += x_bot * float(u_bot.sum())
+        self._uu += float(u_bot @ u_bot)
+        self._usum += float(u_bot.sum())
+        if self.plates == 2:
+            self._xx += S * x_top * x_top
+            self._xu += x_top * float(u_top.sum())
+            self._uu += float(u_top @ u_top)
+            self._usum += float(u_top.sum())
         self.n_samples += S
 
     def train(self, **fit_kw) -> TrainingStep:
@@ -250,8 +264,9 @@ class SurrogateTrainer:
         nE = S * len(self.cells)
         cons = [fit_stats(S * self._BtB[:k, :k], self._hE[:k], self._EE, self._Esum, nE, **fit_kw)
                 for k in range(self.max_order + 1)]
-        no_slip = fit_stats(np.zeros((0, 0)), np.zeros(0), self._uu, self._usum, 2 * S, **fit_kw)
-        slip = fit_stats(np.array([[self._xx]]), np.array([self._xu]), self._uu, self._usum, 2 * S,
+        nw = self.plates * S
+        no_slip = fit_stats(np.zeros((0, 0)), np.zeros(0), self._uu, self._usum, nw, **fit_kw)
+        slip = fit_stats(np.array([[self._xx]]), np.array([self._xu]), self._uu, self._usum, nw,
                          **fit_kw)
         step = TrainingStep(S, [no_slip, slip], cons,
                             probabilities([no_slip.log_evidence, slip.log_evidence]),

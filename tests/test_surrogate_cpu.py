@@ -171,3 +171,26 @@ def test_rejects_bad_windows():
 def test_table_lookup_matches_oracle():
     for kn in (0.01, 0.02, 0.03, 0.07, 0.1, 0.14, 0.15, 0.3, 0.7, 1.0, 2.2, 5.0, 40.0):
         assert sg.table_exponents(kn) == ref.exponents(kn)
+
+
+def test_patch_training_matches_oracle():
+    """A patch of the hybrid: 25 cells of width 0.004 next to the bottom
+    plate, the last 5 a buffer left out of the constitutive targets, and
+    the bottom plate's wall velocity alone."""
+    kn, F, C, dy, ntr = 0.05, 0.0084, 25, 0.004, 20
+    rng = np.random.default_rng(12)
+    y = (np.arange(C) + 0.5) * dy
+    c = 2 * kn / math.sqrt(math.pi)
+    ux = 0.8 * F + F / c * y * (1 - y) + rng.normal(scale=0.004, size=(150, C))
+    pxy = 2 * F * (y - 0.5) + rng.normal(scale=0.003, size=(150, C))
+    t = sg.SurrogateTrainer(kn, F, C, cells=np.arange(ntr), dy=dy, plates=1)
+    t.add(ux, pxy)
+    step = t.train()
+    us, Ps = list(ux), list(pxy)
+    for k in range(4):
+        r = ref.bayesian_ridge(*ref.constitutive_system(us, Ps, kn, k, dy=dy, n_train=ntr))
+        assert_posterior_equal(step.constitutive[k], r, f"C_{k}")
+    for slip in (False, True):
+        r = ref.bayesian_ridge(*ref.slip_system(us, F, slip, plates=1))
+        assert_posterior_equal(step.boundary[int(slip)], r, "slip" if slip else "no-slip")
+    assert step.boundary[1].n_data == 150
