@@ -194,7 +194,7 @@ template <class R> __device__ __forceinline__ R time_to_wall(const InstDesc& d, 
 // plate (top or not) and the time left when it is reached are returned.  In
 // an open instance the top is the open boundary: a particle reaching it
 // leaves the domain (returns true with gone set; its state is then void).
-template <class R>
+template <class R, bool kOpen>
 __device__ __forceinline__ bool flight_start(const InstDesc& d, R& y, R& vx, R vy, R& t_left,
                                              bool& top, bool& gone) {
     const R H = (R)d.H, g = (R)d.g, t = (R)d.dt;
@@ -207,7 +207,7 @@ __device__ __forceinline__ bool flight_start(const InstDesc& d, R& y, R& vx, R v
         return true;
     }
     top = vy > R(0);
-    if (top && d.open) {
+    if (kOpen && top && d.open) {
         gone = true;
         return true;
     }
@@ -219,7 +219,7 @@ __device__ __forceinline__ bool flight_start(const InstDesc& d, R& y, R& vx, R v
 // t left: re-emission, further flight and any later hits (draw h of the
 // particle's wall stream at its h-th hit).  The incoming y, vx, vy, vz are
 // not read.  Returns the number of hits.
-template <class R>
+template <class R, bool kOpen>
 __device__ __forceinline__ int flight_from_wall(const InstDesc& d, uint32_t step, uint32_t slot,
                                                 bool top, R t, R& y, R& vx, R& vy, R& vz,
                                                 bool& gone) {
@@ -239,7 +239,7 @@ __device__ __forceinline__ int flight_from_wall(const InstDesc& d, uint32_t step
             break;
         }
         top = vy > R(0);
-        if (top && d.open) {
+        if (kOpen && top && d.open) {
             gone = true;
             break;
         }
@@ -252,7 +252,7 @@ __device__ __forceinline__ int flight_from_wall(const InstDesc& d, uint32_t step
 
 // The whole flight of one step as one loop (the same arithmetic as
 // flight_start followed by flight_from_wall).  Returns the number of hits.
-template <class R>
+template <class R, bool kOpen>
 __device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32_t slot, R& y,
                                         R& vx, R& vy, R& vz, bool& gone) {
     const R H = (R)d.H, g = (R)d.g, sd = (R)d.sqrt_tw;
@@ -266,7 +266,7 @@ __device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32
             break;
         }
         const bool top = vy > R(0);
-        if (top && d.open) {
+        if (kOpen && top && d.open) {
             gone = true;
             break;
         }
@@ -292,13 +292,15 @@ template <class R> __device__ __forceinline__ int cell_of(const InstDesc& d, R y
 
 // Sort key after a flight: the particle's cell's key, or, for a particle that
 // left through an open boundary, the instance's last key (past every cell).
-template <class R> __device__ __forceinline__ int key_of(const InstDesc& d, R y, bool gone) {
-    return gone ? d.nkeys - 1 : (cell_of<R>(d, y) >> d.key_shift);
+// The open-boundary branches of the particle kernels are compiled in only
+// for launches over lanes that hold an open instance (kOpen).
+template <class R, bool kOpen> __device__ __forceinline__ int key_of(const InstDesc& d, R y, bool gone) {
+    return (kOpen && gone) ? d.nkeys - 1 : (cell_of<R>(d, y) >> d.key_shift);
 }
 
 // Slots holding particles during the current step.
-__device__ __forceinline__ int slots_used(const InstDesc& d) {
-    return d.open ? d.os->n_used : d.N;
+template <bool kOpen> __device__ __forceinline__ int slots_used(const InstDesc& d) {
+    return (kOpen && d.open) ? d.os->n_used : d.N;
 }
 
 template <class R, bool kMove>
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_hist(const InstDesc* 
         if (kMove) {
             R y = b.y[p], vx = b.vx[p], vy = b.vy[p], vz = b.vz[p];
             bool gone = false;  // debug paths run closed instances only
-            const int h = move_one<R>(d, (uint32_t)s, (uint32_t)p, y, vx, vy, vz, gone);
+            const int h = move_one<R, false>(d, (uint32_t)s, (uint32_t)p, y, vx, vy, vz, gone);
             b.y[p] = y;
             b.vx[p] = vx;
             if (h) {
@@ -432,7 +434,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
             }
             run += d.kcount[c];
         }
-        if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != slots_used(d))
+        if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != slots_used<true>(d))
             atomicOr(&d.sc->status, 2);
     }
     __syncthreads();
@@ -616,15 +618,15 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
 
 // Flight of the position alone: the sort key of the y that move_one would
 // produce.
-template <class R>
+template <class R, bool kOpen>
 __device__ __forceinline__ int flight_key(const InstDesc& d, uint32_t step, uint32_t slot, R y, R vy) {
     R vx = R(0), vz = R(0);
     bool gone = false;
-    move_one<R>(d, step, slot, y, vx, vy, vz, gone);
-    return key_of<R>(d, y, gone);
+    move_one<R, kOpen>(d, step, slot, y, vx, vy, vz, gone);
+    return key_of<R, kOpen>(d, y, gone);
 }
 
-template <class R>
+template <class R, bool kOpen>
 __global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __restrict__ descs,
                                                            const int2* __restrict__ work) {
     extern __shared__ int hist[];
@@ -636,7 +638,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __re
     const int64_t s = d.sc->step_done + 1;
     const P4<R> b = particles<R>(d, (int)((s - 1) & 1));
     const int start = w.y * d.tile_items;
-    const int end = min(start + d.tile_items, slots_used(d));
+    const int end = min(start + d.tile_items, slots_used<kOpen>(d));
     constexpr int U = 4;
     for (int p0 = start + (int)threadIdx.x; p0 < end; p0 += U * kParticleThreads) {
         R y[U], vy[U];
@@ -652,7 +654,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __re
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = p0 + u * kParticleThreads;
-            if (p < end) atomicAdd(&hist[flight_key<R>(d, (uint32_t)s, (uint32_t)p, y[u], vy[u])], 1);
+            if (p < end) atomicAdd(&hist[flight_key<R, kOpen>(d, (uint32_t)s, (uint32_t)p, y[u], vy[u])], 1);
         }
     }
     __syncthreads();
@@ -674,7 +676,7 @@ template <class R> struct ScatterRegs {
 // then reads, moves and ranks round by round.  A
 // sorted position outside [0, N) (only possible if the counts and this pass
 // disagreed) is clamped and flagged.
-template <class R>
+template <class R, bool kOpen>
 __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDesc* __restrict__ descs,
                                                                   const int2* __restrict__ work,
                                                                   int stage_max) {
@@ -689,7 +691,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
     const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
     const P4<R> dst = particles<R>(d, (int)(s & 1));
     const int start = w.y * d.tile_items;
-    const int end = min(start + d.tile_items, slots_used(d));
+    const int end = min(start + d.tile_items, slots_used<kOpen>(d));
     const bool staged = d.tile_items <= stage_max;
     int* delta = tables + kScatterWaves * nk;
     int* stage_pos = delta + nk;
@@ -740,7 +742,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
             bool hit = false, top = false, gone = false;
             R tl = R(0);
             jq[k] = 0;
-            if (i < q1) hit = !flight_start<R>(d, ry[k], rx[k], rv[k], tl, top, gone);
+            if (i < q1) hit = !flight_start<R, kOpen>(d, ry[k], rx[k], rv[k], tl, top, gone);
             if (gone) gonem |= 1u << k;
             const unsigned long long hm = __ballot(hit);
             if (hit) {
@@ -752,8 +754,8 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
                     hitm |= 1u << k;
                 } else {
                     bool gone2 = false;
-                    flight_from_wall<R>(d, (uint32_t)s, (uint32_t)i, top, tl, ry[k], rx[k], rv[k], rz[k],
-                                        gone2);
+                    flight_from_wall<R, kOpen>(d, (uint32_t)s, (uint32_t)i, top, tl, ry[k], rx[k], rv[k],
+                                               rz[k], gone2);
                     if (gone2) gonem |= 1u << k;
                 }
             }
@@ -768,8 +770,8 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
                 const R tt = qt[j];
                 R y = R(0), vx = R(0), vy = R(0), vz = R(0);
                 bool gone3 = false;
-                flight_from_wall<R>(d, (uint32_t)s, (uint32_t)qslot[j], tt > R(0), tt > R(0) ? tt : -tt,
-                                    y, vx, vy, vz, gone3);
+                flight_from_wall<R, kOpen>(d, (uint32_t)s, (uint32_t)qslot[j], tt > R(0),
+                                           tt > R(0) ? tt : -tt, y, vx, vy, vz, gone3);
                 qy[j] = gone3 ? R(-1) : y;  // a flight ends at y >= 0: -1 marks one that left
                 qx[j] = vx;
                 qv[j] = vy;
@@ -788,17 +790,17 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
                 rx[k] = qx[j];
                 rv[k] = qv[j];
                 rz[k] = qz[j];
-                if (ry[k] < R(0)) gonem |= 1u << k;
+                if (kOpen && ry[k] < R(0)) gonem |= 1u << k;
             }
             if (i < q1) {
                 bad |= !(isfinite(rx[k]) && isfinite(rv[k]) && isfinite(rz[k]));
-                key[k] = key_of<R>(d, ry[k], (gonem >> k) & 1u);
+                key[k] = key_of<R, kOpen>(d, ry[k], (gonem >> k) & 1u);
                 atomicAdd(&mine[key[k]], 1);
             }
         }
     } else {
         for (int i = q0 + lane; i < q1; i += 64)
-            atomicAdd(&mine[flight_key<R>(d, (uint32_t)s, (uint32_t)i, src.y[i], src.vy[i])], 1);
+            atomicAdd(&mine[flight_key<R, kOpen>(d, (uint32_t)s, (uint32_t)i, src.y[i], src.vy[i])], 1);
     }
     __syncthreads();
     for (int c = threadIdx.x; c < nk; c += blockDim.x) {
@@ -886,9 +888,9 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
                 vy = src.vy[i];
                 vz = src.vz[i];
                 bool gone = false;
-                move_one<R>(d, (uint32_t)s, (uint32_t)i, y, vx, vy, vz, gone);
+                move_one<R, kOpen>(d, (uint32_t)s, (uint32_t)i, y, vx, vy, vz, gone);
                 bad |= !(isfinite(vx) && isfinite(vy) && isfinite(vz));
-                kk = key_of<R>(d, y, gone);
+                kk = key_of<R, kOpen>(d, y, gone);
             }
             place(valid, kk, y, vx, vy, vz);
         }
@@ -1865,10 +1867,14 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
     };
     mark(0);
     if ((phase & kPhaseMove) && (phase & kPhaseSort)) {
-        if (w.has_open)
+        if (w.has_open) {
             hipLaunchKernelGGL((k_inject<R>), dim3(w.n_inst), dim3(256), 0, st, w.desc);
-        hipLaunchKernelGGL((k_count<R>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds, st, w.desc,
-                           w.tiles);
+            hipLaunchKernelGGL((k_count<R, true>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds,
+                               st, w.desc, w.tiles);
+        } else {
+            hipLaunchKernelGGL((k_count<R, false>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds,
+                               st, w.desc, w.tiles);
+        }
         mark(1);
         hipLaunchKernelGGL(k_colsum, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
         mark(2);
@@ -1876,9 +1882,14 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
         mark(3);
         hipLaunchKernelGGL(k_colprefix, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
         mark(4);
-        hipLaunchKernelGGL((k_move_scatter<R>), dim3(w.n_tiles), dim3(kParticleThreads),
-                           scatter_lds_bytes(mode, w.max_cc, w.stage_max), st, w.desc, w.tiles,
-                           w.stage_max);
+        if (w.has_open)
+            hipLaunchKernelGGL((k_move_scatter<R, true>), dim3(w.n_tiles), dim3(kParticleThreads),
+                               scatter_lds_bytes(mode, w.max_cc, w.stage_max), st, w.desc, w.tiles,
+                               w.stage_max);
+        else
+            hipLaunchKernelGGL((k_move_scatter<R, false>), dim3(w.n_tiles), dim3(kParticleThreads),
+                               scatter_lds_bytes(mode, w.max_cc, w.stage_max), st, w.desc, w.tiles,
+                               w.stage_max);
     } else {
         step_kernels_debug<R>(w, mode, phase, st, mark);
     }
@@ -1955,10 +1966,14 @@ hipError_t configure_kernels(size_t max_dynamic_lds) {
     set((const void*)k_move_hist<double, false>);
     set((const void*)k_scatter<float>);
     set((const void*)k_scatter<double>);
-    set((const void*)k_count<float>);
-    set((const void*)k_count<double>);
-    set((const void*)k_move_scatter<float>);
-    set((const void*)k_move_scatter<double>);
+    set((const void*)k_count<float, false>);
+    set((const void*)k_count<double, false>);
+    set((const void*)k_count<float, true>);
+    set((const void*)k_count<double, true>);
+    set((const void*)k_move_scatter<float, false>);
+    set((const void*)k_move_scatter<double, false>);
+    set((const void*)k_move_scatter<float, true>);
+    set((const void*)k_move_scatter<double, true>);
     return e;
 }
 

@@ -109,28 +109,33 @@ class OneWay:
         """MMS velocity against the benchmark at the benchmark's cells."""
         if self.benchmark is None:
             return {}
-        b = self.benchmark
-        model = self.solution.model
-        u = model.velocity(b.y)
-        scale = float(np.max(np.abs(b.ux)))
-        err = u - b.ux
-        step = self.trainer.history[-1]
-        # spread of the MMS velocity at the benchmark's cells
-        from .macro import velocity_basis
-        B = velocity_basis(b.y, model.kn, model.force, model.b)
-        cov = np.zeros((1 + len(model.b), 1 + len(model.b)))
-        if self.solution.slip:
-            cov[0, 0] = step.boundary[1].S[0, 0]
-        cov[1:, 1:] = step.constitutive[self.solution.order].S
-        sd = np.sqrt(np.einsum("ij,jk,ik->i", B, cov, B))
-        z = err / np.sqrt(sd ** 2 + b.ux_se ** 2)
-        return dict(max_rel_err=float(np.max(np.abs(err)) / scale),
-                    rms_rel_err=float(np.sqrt(np.mean(err ** 2)) / scale),
-                    wall_rel_err=float(max(abs(err[0]), abs(err[-1])) / scale),
-                    frac_within_2sd=float(np.mean(np.abs(z) <= 2.0)),
-                    mass_flow_mms=float(model.mass_flow()), mass_flow_bench=b.mass_flow,
-                    mass_flow_bench_se=b.mass_flow_se,
-                    mass_flow_rel_err=float(model.mass_flow() / b.mass_flow - 1.0))
+        return compare_with_benchmark(self.solution, self.trainer.history[-1], self.benchmark)
+
+
+def compare_with_benchmark(solution: MmsSolution, step: sg.TrainingStep, b: Benchmark) -> dict:
+    """Errors of a macro solution's velocity at the benchmark's cells,
+    relative to the benchmark's largest velocity, and the fraction of cells
+    within two combined standard deviations (the posterior spread of the
+    macro velocity and the benchmark's standard error)."""
+    from .macro import velocity_basis
+    model = solution.model
+    u = model.velocity(b.y)
+    scale = float(np.max(np.abs(b.ux)))
+    err = u - b.ux
+    B = velocity_basis(b.y, model.kn, model.force, model.b)
+    cov = np.zeros((1 + len(model.b), 1 + len(model.b)))
+    if solution.slip:
+        cov[0, 0] = step.boundary[1].S[0, 0]
+    cov[1:, 1:] = step.constitutive[solution.order].S
+    sd = np.sqrt(np.einsum("ij,jk,ik->i", B, cov, B))
+    z = err / np.sqrt(sd ** 2 + b.ux_se ** 2)
+    return dict(max_rel_err=float(np.max(np.abs(err)) / scale),
+                rms_rel_err=float(np.sqrt(np.mean(err ** 2)) / scale),
+                wall_rel_err=float(max(abs(err[0]), abs(err[-1])) / scale),
+                frac_within_2sd=float(np.mean(np.abs(z) <= 2.0)),
+                mass_flow_mms=float(model.mass_flow()), mass_flow_bench=b.mass_flow,
+                mass_flow_bench_se=b.mass_flow_se,
+                mass_flow_rel_err=float(model.mass_flow() / b.mass_flow - 1.0))
 
 
 def one_way(kn: float, training_steps: int = 1000, samples_per_step: int = 100,
