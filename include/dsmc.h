@@ -205,6 +205,14 @@ int dsmc_set_inflow(dsmc_handle *h, double u, double dudy, double temperature, d
 int dsmc_open_state(dsmc_handle *h, int32_t *n_live, int64_t *n_injected, int64_t *n_removed,
                     double *inj_remainder);
 
+/* Restore what dsmc_open_state returned (a checkpoint of an open instance:
+ * this first, so that dsmc_set_state takes n_live particles, then
+ * dsmc_set_state and dsmc_set_cells; the inflow is set again with
+ * dsmc_set_inflow).  INVALID_ARG if the instance is closed, n_live exceeds
+ * the slots, a count is negative or the remainder is outside [0, 1). */
+int dsmc_set_open_state(dsmc_handle *h, int32_t n_live, int64_t n_injected, int64_t n_removed,
+                        double inj_remainder);
+
 /* Per collision cell (n_cells*n_sub each, host): crmax, the NTC remainder,
  * particle count and slot offset after the last sort.  NULL skips. */
 int dsmc_get_cells(dsmc_handle *h, double *crmax, double *rem, int32_t *count,

@@ -1000,6 +1000,26 @@ int dsmc_set_inflow(dsmc_handle* h, double u, double dudy, double temperature, d
     return DSMC_OK;
 }
 
+int dsmc_set_open_state(dsmc_handle* h, int32_t n_live, int64_t n_injected, int64_t n_removed,
+                        double inj_remainder) {
+    if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
+    if (!h->plan.open) return fail(&h->err, DSMC_ERR_INVALID_ARG, "the instance has no open boundary");
+    if (n_live < 0 || n_live > h->plan.ncap || n_injected < 0 || n_removed < 0 ||
+        !(std::isfinite(inj_remainder) && inj_remainder >= 0.0 && inj_remainder < 1.0))
+        return fail(&h->err, DSMC_ERR_INVALID_ARG, "open state out of range");
+    const int r = sync_check(h);
+    if (r) return r;
+    OpenState os;
+    HIP_TRY(&h->err, hipMemcpy(&os, h->desc.os, sizeof os, hipMemcpyDeviceToHost));
+    os.n_live = n_live;
+    os.n_used = n_live;
+    os.n_injected = n_injected;
+    os.n_deleted = n_removed;
+    os.inj_rem = inj_remainder;
+    HIP_TRY(&h->err, hipMemcpy(h->desc.os, &os, sizeof os, hipMemcpyHostToDevice));
+    return DSMC_OK;
+}
+
 int dsmc_open_state(dsmc_handle* h, int32_t* n_live, int64_t* n_injected, int64_t* n_removed,
                     double* inj_remainder) {
     if (!h) return fail(nullptr, DSMC_ERR_INVALID_ARG, "handle is NULL");
@@ -1039,7 +1059,11 @@ int dsmc_set_cells(dsmc_handle* h, const double* crmax, const double* rem, const
             if (count[i] < 0 || offset[i] != tot) return fail(&h->err, DSMC_ERR_INVALID_ARG, "offsets must be the exclusive scan of counts");
             tot += count[i];
         }
-        if (tot != h->plan.N) return fail(&h->err, DSMC_ERR_INVALID_ARG, "counts must add up to N");
+        int32_t n_live = 0;
+        r = live_count(h, &n_live);
+        if (r) return r;
+        if (tot != n_live)
+            return fail(&h->err, DSMC_ERR_INVALID_ARG, "counts must add up to the particles held");
     } else if (count || offset) {
         return fail(&h->err, DSMC_ERR_INVALID_ARG, "count and offset must be given together");
     }

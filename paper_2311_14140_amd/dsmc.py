@@ -37,7 +37,7 @@ EXPORTS = (
     "dsmc_group_create", "dsmc_group_add", "dsmc_group_remove", "dsmc_group_step",
     "dsmc_group_sync", "dsmc_group_size", "dsmc_group_lanes", "dsmc_group_destroy", "dsmc_group_set_tuning",
     "dsmc_group_autotune", "dsmc_profile_step", "dsmc_group_sample", "dsmc_set_inflow",
-    "dsmc_open_state",
+    "dsmc_open_state", "dsmc_set_open_state",
 )
 
 
@@ -97,6 +97,7 @@ def _load():
         "dsmc_set_inflow": [vp, ct.c_double, ct.c_double, ct.c_double, ct.c_double],
         "dsmc_open_state": [vp, ct.POINTER(i32), ct.POINTER(i64), ct.POINTER(i64),
                             ct.POINTER(ct.c_double)],
+        "dsmc_set_open_state": [vp, i32, i64, i64, ct.c_double],
         "dsmc_group_destroy": [vp],
         "dsmc_group_set_tuning": [vp, i32, i32],
         "dsmc_group_autotune": [vp, ct.POINTER(i32), ct.POINTER(i32)],
@@ -267,6 +268,11 @@ class Solver:
         _check(lib.dsmc_open_state(self._h, ct.byref(n), ct.byref(a), ct.byref(b), ct.byref(r)),
                self._h)
         return dict(n_live=n.value, n_injected=a.value, n_deleted=b.value, inj_rem=r.value)
+
+    def set_open_state(self, n_live: int, n_injected: int, n_deleted: int, inj_rem: float):
+        """Restore an open instance's boundary state (before set_state)."""
+        _check(lib.dsmc_set_open_state(self._h, int(n_live), int(n_injected), int(n_deleted),
+                                       float(inj_rem)), self._h)
 
     def live(self) -> int:
         return self.open_state()["n_live"] if self.open else self.N
