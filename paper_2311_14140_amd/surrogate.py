@@ -322,7 +322,7 @@ class TrainingRun:
 
 def train_on_gpu(params_list, training_steps: int, samples_per_step: int = 100,
                  steps_per_sample: int = 100, grouped: bool = True, flows=None,
-                 keep_windows: bool = False) -> TrainingRun:
+                 keep_windows: bool = False, on_step=None) -> TrainingRun:
     """Run the training schedule on the GPU for every parameter set in
     ``params_list``: step through the transient, then per training step
     collect ``samples_per_step`` windows of ``steps_per_sample`` steps from
@@ -332,7 +332,8 @@ def train_on_gpu(params_list, training_steps: int, samples_per_step: int = 100,
     per instance).  Instances of one flow (same Kn, force and cells, other
     seeds) are independent realisations, so pooling R of them gives R
     samples per window: the paper's sample count in 1/R of its steps.
-    With ``grouped`` all instances advance in one batched group."""
+    With ``grouped`` all instances advance in one batched group.
+    ``on_step(i, run)`` is called after training step i."""
     from . import dsmc
     flows = list(range(len(params_list))) if flows is None else list(flows)
     if len(flows) != len(params_list):
@@ -383,6 +384,8 @@ def train_on_gpu(params_list, training_steps: int, samples_per_step: int = 100,
                 t.train()
             run.seconds_train += time.perf_counter() - t0
             run.windows += samples_per_step
+            if on_step is not None:
+                on_step(len(trainers[0].history) - 1, run)
         return run
     finally:
         if group is not None:
