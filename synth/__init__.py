@@ -156,6 +156,17 @@ def benchmark_case(kn: float, replica: int = 0, precision: int = FP32_FAST) -> P
         particles_per_cell=BENCHMARK_PPC, seed=seed_of(6, int(round(1000 * kn)), replica))
 
 
+# A patch of the hybrid at Kn = 0.1 (two mean free paths of cells of 0.005
+# plus a 5-cell buffer: 45 cells, wall at 0, open boundary at 0.225) with the
+# Chapman-Enskog inflow of a slip-flow macro state there (sigma_P 0.8, no
+# stress correction): the open-boundary workload of the parity tests.
+PATCH0 = Params(kn=0.1, body_force=training_force(0.1), n_cells=45, particles_per_cell=50,
+                n_transient=500, seed=seed_of(11), precision=FP64_DETERMINISTIC,
+                domain_length=0.225)
+PATCH0_INFLOW = dict(u=0.0333, dudy=0.069)
+PATCH0_STEPS = 6500
+
+
 WORKLOADS = {
     "cfg0": (CONFIG0, CONFIG0_STEPS),
     "cfg1": (CONFIG1, CONFIG1_STEPS),

@@ -46,15 +46,22 @@ SCHEDULES = {
     # workload: (params, workload index for seeds, transient, sampling steps)
     "cfg0": (synth.CONFIG0, 0, 1000, 1000),
     "cfg1": (synth.CONFIG1, 1, 1000, 20000),
+    # an open patch of the hybrid with a fixed Chapman-Enskog inflow
+    "patch0": (synth.PATCH0, 11, synth.PATCH0.n_transient,
+               synth.PATCH0_STEPS - synth.PATCH0.n_transient),
 }
+INFLOWS = {"patch0": synth.PATCH0_INFLOW}
+EXTRA = {"patch0": ("pxy_mid",)}
 
 
-def run_replica(params, transient, sampling):
+def run_replica(params, transient, sampling, inflow=None, extra=()):
     o = oracle.Oracle(params.with_(n_transient=transient))
+    if inflow:
+        o.set_inflow(**inflow)
     o.step(transient + sampling)
     e = o.estimators()
     assert e["n_sampled_steps"] == sampling
-    return {q: e[q].copy() for q in QUANTITIES}, e["mass_flow"]
+    return {q: e[q].copy() for q in QUANTITIES + tuple(extra)}, e["mass_flow"]
 
 
 def bin_means(profile, bins=MIX_BINS):
@@ -105,14 +112,17 @@ def main():
     if args.workload == "cfg3":
         return main_mix(args)
     base, k, transient, sampling = SCHEDULES[args.workload]
+    inflow = INFLOWS.get(args.workload)
+    extra = EXTRA.get(args.workload, ())
     reps = [base.with_(seed=synth.seed_of(k, 0, r))
             for r in range(args.first, args.first + args.replicas)]
     t0 = time.time()
-    out = {q: [] for q in QUANTITIES}
+    out = {q: [] for q in QUANTITIES + extra}
     Q = []
     with ThreadPoolExecutor(args.workers) as ex:
-        for i, (prof, q) in enumerate(ex.map(lambda p: run_replica(p, transient, sampling), reps)):
-            for name in QUANTITIES:
+        for i, (prof, q) in enumerate(ex.map(lambda p: run_replica(p, transient, sampling, inflow,
+                                                                   extra), reps)):
+            for name in QUANTITIES + extra:
                 out[name].append(prof[name])
             Q.append(q)
             print(f"replica {args.first + i}: mass flow {q:.6f} ({time.time() - t0:.0f} s)",
@@ -120,11 +130,11 @@ def main():
     src = open(oracle.SRC, "rb").read()
     meta = dict(workload=args.workload, params=base.as_dict(), transient=transient,
                 sampling_steps=sampling, replicas=args.replicas, first_replica=args.first,
-                seed_rule="synth.seed_of(%d, 0, r)" % k,
+                seed_rule="synth.seed_of(%d, 0, r)" % k, inflow=inflow,
                 oracle_sha256=hashlib.sha256(src).hexdigest())
     path = os.path.join(HERE, f"oracle_{args.workload}_r{args.first}_{args.first + args.replicas}.npz")
     np.savez_compressed(path, mass_flow=np.array(Q),
-                        **{q: np.array(out[q]) for q in QUANTITIES}, meta=json.dumps(meta))
+                        **{q: np.array(out[q]) for q in QUANTITIES + extra}, meta=json.dumps(meta))
     print("wrote", path, flush=True)
 
 

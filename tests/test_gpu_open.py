@@ -205,3 +205,35 @@ def test_open_patch_checkpoint_resumes_bit_exactly(D, prec_name):
         assert np.array_equal(np.asarray(x), np.asarray(y))
     assert got[2] == want[2]
     assert got[1].shape == want[1].shape
+
+
+@pytest.mark.parametrize("prec_name", ["DSMC_FP32_FAST", "DSMC_FP64_FAST"])
+def test_fast_open_patch_matches_oracle_replicas(D, prec_name):
+    """64 replicas of the Kn = 0.1 hybrid patch with a fixed Chapman-Enskog
+    inflow (500 + 6000 steps) against 64 oracle replicas: every cell's
+    density, velocity, temperature, both shear stresses and heat flux by the
+    Welch rule of the other statistical parity tests, and the mass flow."""
+    import os
+    from test_gpu_parity_fp32 import assert_profiles_agree, welch
+    d = np.load(os.path.join(os.path.dirname(__file__), "golden", "oracle_patch0_r0_64.npz"))
+    quant = ("n", "ux", "T", "pxy", "qx", "pxy_mid")
+    ref = {q: d[q] for q in quant}
+    R = ref["ux"].shape[0]
+    base = synth.PATCH0.with_(precision=getattr(D, prec_name))
+    sols = [D.Solver(base.with_(seed=synth.seed_of(11, 0, 1000 + r))) for r in range(R)]
+    g = D.Group()
+    for s in sols:
+        s.set_inflow(**synth.PATCH0_INFLOW)
+        g.add(s)
+    g.step(synth.PATCH0_STEPS)
+    es = g.sample()
+    g.close()
+    for s in sols:
+        s.close()
+    gpu = {q: np.array([e[q] for e in es]) for q in quant}
+    assert all(e["n_sampled_steps"] == synth.PATCH0_STEPS - synth.PATCH0.n_transient for e in es)
+    assert_profiles_agree(gpu, ref, quant)
+    Q = np.array([e["mass_flow"] for e in es])
+    zq, _, se = welch(Q[:, None], d["mass_flow"][:, None])
+    _say(f"{prec_name}: mass flow {Q.mean():.6f} vs oracle {d['mass_flow'].mean():.6f} (z {zq[0]:.2f})")
+    assert abs(zq[0]) < 3.5
