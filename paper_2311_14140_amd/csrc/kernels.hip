@@ -109,64 +109,58 @@ __global__ void k_init(const InstDesc* __restrict__ descs) {
 // Particles entering an open instance through its top at the start of a step
 // (the hybrid's inflow: the Chapman-Enskog distribution of pure shear at the
 // macro state imposed there, Sec. 2): floor(expected + carried remainder) of
-// them, placed after the live slots of the step's source buffer.  Injection k
-// of step s draws from tag kTagInject, entity k.  Per attempt one call gives
-// the acceptance uniform and the flux-weighted inward speed sqrt(-2 T ln U),
-// a polar pair from the following calls the thermal x and z velocities, and
-// the attempt is kept with probability (1 - a C_x C_y) / A, C = c / sqrt(2T);
-// a last call gives the fraction of the step spent inside.  The particle
-// starts where a straight flight of the whole step brings it across the
-// boundary at that moment, with the force's x velocity gain of the outside
-// part taken off, so the ordinary move delivers it with the drawn velocity at
-// the boundary.  Drawn in FP64 for every precision, then stored.
+// them, limited to the free slots, take the slots after the live ones of the
+// step's source buffer.  The count pass draws them there (no launch of their
+// own) and k_scan, once per instance, books their number and the remainder
+// carried on.  Injection k of step s draws from tag kTagInject, entity k.
+// Per attempt one call gives the acceptance uniform and the flux-weighted
+// inward speed sqrt(-2 T ln U), a polar pair from the following calls the
+// thermal x and z velocities, and the attempt is kept with probability
+// (1 - a C_x C_y) / A, C = c / sqrt(2T); a last call gives the fraction of
+// the step spent inside.  The particle starts where a
+// straight flight of the whole step brings it across the boundary at that
+// moment, with the force's x velocity gain of the outside part taken off, so
+// the ordinary move delivers it with the drawn velocity at the boundary.
+
+// Injections of the coming step of an open instance holding `live`
+// particles, the remainder carried past it, and whether the slots ran out.
+__device__ __forceinline__ int injections(const InstDesc& d, int live, double& rem_next,
+                                          bool& clipped) {
+    const double m = d.os->inj_expected + d.os->inj_rem;
+    const double f = floor(m);
+    rem_next = m - f;
+    int64_t n = (int64_t)f;
+    clipped = (int64_t)live + n > (int64_t)d.ncap;
+    if (clipped) n = (int64_t)d.ncap - (int64_t)live;
+    return (int)n;
+}
+
+// State of injection k of step s: drawn in FP64 for every precision, then
+// rounded to the storage precision.
 template <class R>
-__global__ __launch_bounds__(256) void k_inject(const InstDesc* __restrict__ descs) {
-    const InstDesc& d = descs[blockIdx.x];
-    if (!d.open) return;
-    __shared__ int sh_n, sh_live;
-    OpenState* os = d.os;
-    if (threadIdx.x == 0) {
-        const int live = os->n_live;
-        const double m = os->inj_expected + os->inj_rem;
-        const double f = floor(m);
-        os->inj_rem = m - f;
-        int64_t n = (int64_t)f;
-        if ((int64_t)live + n > (int64_t)d.ncap) {
-            atomicOr(&d.sc->status, 8);
-            n = (int64_t)d.ncap - (int64_t)live;
-        }
-        os->n_injected += n;
-        os->n_used = live + (int)n;
-        sh_n = (int)n;
-        sh_live = live;
-    }
-    __syncthreads();
-    const int n = sh_n, live = sh_live;
-    const int64_t s = d.sc->step_done + 1;
-    const P4<R> b = particles<R>(d, (int)((s - 1) & 1));
+__device__ __forceinline__ void inject_state(const InstDesc& d, uint32_t s, int k, R& y, R& vx,
+                                             R& vy, R& vz) {
+    const OpenState* os = d.os;
     const double sqrt_tin = os->sqrt_tin, vt = os->vt_in, a = os->ce_a, A = os->ce_A;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        Stream st(d.key0, d.key1, (uint32_t)s, (uint32_t)k, 0u, kTagInject);
-        double sp, tx, tz;
-        for (;;) {
-            double ua, ub;
-            Num<double>::uni2(st.next(), ua, ub);
-            sp = __builtin_sqrt(-2.0 * series_log(ub)) * sqrt_tin;
-            normal_pair<double>(st, sqrt_tin, tx, tz);
-            const double cx = tx / vt;
-            const double cy = -sp / vt;
-            const double gam = 1.0 - a * (cx * cy);
-            if (ua * A < gam) break;
-        }
-        double ut, unused;
-        Num<double>::uni2(st.next(), ut, unused);
-        const double outside = d.dt - ut * d.dt;
-        const int q = live + k;
-        b.y[q] = (R)(d.H + sp * outside);
-        b.vx[q] = (R)((os->u_in + tx) - d.g * outside);
-        b.vy[q] = (R)(-sp);
-        b.vz[q] = (R)tz;
+    Stream st(d.key0, d.key1, s, (uint32_t)k, 0u, kTagInject);
+    double sp, tx, tz;
+    for (;;) {
+        double ua, ub;
+        Num<double>::uni2(st.next(), ua, ub);
+        sp = __builtin_sqrt(-2.0 * series_log(ub)) * sqrt_tin;
+        normal_pair<double>(st, sqrt_tin, tx, tz);
+        const double cx = tx / vt;
+        const double cy = -sp / vt;
+        const double gam = 1.0 - a * (cx * cy);
+        if (ua * A < gam) break;
     }
+    double ut, unused;
+    Num<double>::uni2(st.next(), ut, unused);
+    const double outside = d.dt - ut * d.dt;
+    y = (R)(d.H + sp * outside);
+    vx = (R)((os->u_in + tx) - d.g * outside);
+    vy = (R)(-sp);
+    vz = (R)tz;
 }
 
 // ------------------------------------------------------------------ move
@@ -298,8 +292,21 @@ template <class R, bool kOpen> __device__ __forceinline__ int key_of(const InstD
     return (kOpen && gone) ? d.nkeys - 1 : (cell_of<R>(d, y) >> d.key_shift);
 }
 
-// Slots holding particles during the current step.
-template <bool kOpen> __device__ __forceinline__ int slots_used(const InstDesc& d) {
+// Slots of the current step: [0, live) hold the particles carried over,
+// [live, used) the injections.  The count pass, before k_scan has booked the
+// step, derives them from the open state; the move-scatter pass reads
+// k_scan's record of the slots in use.
+struct Slots {
+    int live, used;
+};
+template <bool kOpen> __device__ __forceinline__ Slots slots_before_scan(const InstDesc& d) {
+    if (!(kOpen && d.open)) return Slots{d.N, d.N};
+    const int live = d.os->n_live;
+    double rem;
+    bool clipped;
+    return Slots{live, live + injections(d, live, rem, clipped)};
+}
+template <bool kOpen> __device__ __forceinline__ int slots_after_scan(const InstDesc& d) {
     return (kOpen && d.open) ? d.os->n_used : d.N;
 }
 
@@ -385,8 +392,28 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
                                                      int do_scan) {
     const InstDesc& d = descs[blockIdx.x];
     __shared__ int wsum[kScanThreads / 64];
+    __shared__ int sh_used;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (do_scan) {
+        // an open instance's injections of this step (drawn by the particle
+        // passes) are booked here, before its live count is replaced below
+        if (tid == 0) {
+            int used = d.N;
+            if (d.open) {
+                OpenState* os = d.os;
+                const int live = os->n_live;
+                double rem;
+                bool clipped;
+                const int n = injections(d, live, rem, clipped);
+                if (clipped) atomicOr(&d.sc->status, 8);
+                os->inj_rem = rem;
+                os->n_injected += n;
+                used = live + n;
+                os->n_used = used;
+            }
+            sh_used = used;
+        }
+        __syncthreads();
         const int Cc = d.nkeys, nseg = d.nseg;
         const gptr<int32_t> seg = gmem(d.segsum);
         const int per = (Cc + kScanThreads - 1) / kScanThreads;
@@ -434,7 +461,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
             }
             run += d.kcount[c];
         }
-        if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != slots_used<true>(d))
+        if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != sh_used)
             atomicOr(&d.sc->status, 2);
     }
     __syncthreads();
@@ -638,7 +665,9 @@ __global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __re
     const int64_t s = d.sc->step_done + 1;
     const P4<R> b = particles<R>(d, (int)((s - 1) & 1));
     const int start = w.y * d.tile_items;
-    const int end = min(start + d.tile_items, slots_used<kOpen>(d));
+    const Slots sl = slots_before_scan<kOpen>(d);
+    const int end_all = min(start + d.tile_items, sl.used);
+    const int end = min(end_all, sl.live);
     constexpr int U = 4;
     for (int p0 = start + (int)threadIdx.x; p0 < end; p0 += U * kParticleThreads) {
         R y[U], vy[U];
@@ -657,6 +686,18 @@ __global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __re
             if (p < end) atomicAdd(&hist[flight_key<R, kOpen>(d, (uint32_t)s, (uint32_t)p, y[u], vy[u])], 1);
         }
     }
+    // an open instance's injections in this tile: drawn, stored for the
+    // move-scatter pass and counted like the others
+    if (kOpen)
+        for (int p = max(start, sl.live) + (int)threadIdx.x; p < end_all; p += kParticleThreads) {
+            R y, vx, vy, vz;
+            inject_state<R>(d, (uint32_t)s, p - sl.live, y, vx, vy, vz);
+            b.y[p] = y;
+            b.vx[p] = vx;
+            b.vy[p] = vy;
+            b.vz[p] = vz;
+            atomicAdd(&hist[flight_key<R, kOpen>(d, (uint32_t)s, (uint32_t)p, y, vy)], 1);
+        }
     __syncthreads();
     const gptr<int32_t> row = gmem(d.counts) + (size_t)w.y * nk;
     for (int c = threadIdx.x; c < nk; c += blockDim.x) row[c] = hist[c];
@@ -691,7 +732,7 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
     const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
     const P4<R> dst = particles<R>(d, (int)(s & 1));
     const int start = w.y * d.tile_items;
-    const int end = min(start + d.tile_items, slots_used<kOpen>(d));
+    const int end = min(start + d.tile_items, slots_after_scan<kOpen>(d));
     const bool staged = d.tile_items <= stage_max;
     int* delta = tables + kScatterWaves * nk;
     int* stage_pos = delta + nk;
@@ -1868,7 +1909,6 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
     mark(0);
     if ((phase & kPhaseMove) && (phase & kPhaseSort)) {
         if (w.has_open) {
-            hipLaunchKernelGGL((k_inject<R>), dim3(w.n_inst), dim3(256), 0, st, w.desc);
             hipLaunchKernelGGL((k_count<R, true>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds,
                                st, w.desc, w.tiles);
         } else {

@@ -25,7 +25,7 @@ struct Work {
     int max_cc;             // largest sort-key count (LDS of histograms)
     int stage_max;          // tiles of at most this many slots are staged in LDS by the scatter
     int fast_cap;           // particles a fast-collide workgroup stages in LDS
-    int has_open;           // some instance has an open boundary (injection runs)
+    int has_open;           // some instance has an open boundary (open-boundary kernel variants)
 };
 
 void launch_init(const InstDesc& d, const InstDesc* d_desc, Mode mode, hipStream_t s);

@@ -173,6 +173,50 @@ def hybrid(kn: float, force: float | None = None, iterations: int = 16,
     return run
 
 
+def time_patch_group(kn: float, open_boundary: bool = True, replicas: int = 64,
+                     steps: int = 2000, profile_steps: int = 50, dy: float = 0.005,
+                     particles_per_cell: int = 50, u_in: float = 0.03,
+                     dudy_in: float = 0.07) -> dict:
+    """Cost of one step of the hybrid's DSMC: ``replicas`` patches at ``kn``
+    (FP32) batched in one group, with their open boundary and a fixed inflow,
+    or closed at the same size for comparison.  Wall time per step over
+    ``steps`` graph-replayed steps, and device time per kernel slot from
+    ``profile_steps`` eagerly launched steps timed with HIP events."""
+    import synth
+    from . import dsmc
+    patch = patch_for(kn, dy)
+    F = synth.training_force(kn)
+    ps = [synth.Params(kn=kn, body_force=F, n_cells=patch.n_cells,
+                       particles_per_cell=particles_per_cell, n_transient=10,
+                       seed=synth.seed_of(12, r), precision=synth.FP32_FAST,
+                       domain_length=patch.length if open_boundary else 0.0)
+          for r in range(replicas)]
+    solvers, group = [], None
+    try:
+        solvers = [dsmc.Solver(p) for p in ps]
+        group = dsmc.Group()
+        for s in solvers:
+            if open_boundary:
+                s.set_inflow(u=u_in, dudy=dudy_in)
+            group.add(s)
+        group.step(200)
+        group.sync()
+        prof = solvers[0].profile(profile_steps)
+        t0 = time.perf_counter()
+        group.step(steps)
+        group.sync()
+        wall = (time.perf_counter() - t0) / steps
+        live = sum(s.live() for s in solvers)
+    finally:
+        if group is not None:
+            group.close()
+        for s in solvers:
+            s.close()
+    return dict(kn=kn, open=open_boundary, replicas=replicas, patch_cells=patch.n_cells,
+                particles=live, ms_per_step=wall * 1e3, particle_steps_per_s=live / wall,
+                kernel_ms_per_step={k: prof[k] / profile_steps for k in dsmc.Solver.PHASES})
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--kn", type=float, nargs="+", default=[0.1])
@@ -183,7 +227,15 @@ def main():
     ap.add_argument("--bench-steps", type=int, default=10 ** 6)
     ap.add_argument("--bench-replicas", type=int, default=8)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--time-patches", action="store_true",
+                    help="only time the patch group per step, open and closed, at each Kn")
     a = ap.parse_args()
+    if a.time_patches:
+        for kn in a.kn:
+            for open_boundary in (True, False):
+                print(json.dumps(time_patch_group(kn, open_boundary, replicas=a.replicas)),
+                      flush=True)
+        return
     import synth
     from .mms import compare_with_benchmark, run_benchmark
     for kn in a.kn:
