@@ -239,8 +239,10 @@ const char *dsmc_last_error(const dsmc_handle *h);
 /* ---------------------------------------------------------------- batching
  * A group runs many independent instances of one precision together: each
  * phase of a step is one launch over all members, and chunks of steps are
- * replayed from a captured HIP graph.  Per-instance arithmetic and ordering
- * are the same as alone, so results do not depend on the group's make-up. */
+ * replayed from a captured HIP graph; a group of small instances instead runs
+ * each in one workgroup for whole steps (dsmc_group_set_resident).
+ * Per-instance arithmetic and ordering are the same as alone, so results do
+ * not depend on the group's make-up. */
 int dsmc_group_create(void *stream, dsmc_group **out);
 /* Add an instance (INVALID_ARG if it already belongs to a group or its
  * precision differs from the group's). */
@@ -285,6 +287,19 @@ int dsmc_group_destroy(dsmc_group *g);
  * cells into one LDS-staged collide workgroup (default one cell each).
  * 0 keeps the automatic choice.  Results do not depend on either. */
 int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t particles_per_block);
+/* Resident stepping of small instances (on by default).  When every member
+ * of a lane is small -- a fast mode, fewer than 256 particles per collision
+ * cell, at most 256 collision cells (255 for an open instance) and at most
+ * 4096 particle slots in FP32 or 2048 in FP64_FAST -- the lane runs each
+ * member in one workgroup that holds its particles in LDS and performs whole
+ * steps (move, stable sort by cell, collisions, sampling) back to back, as
+ * many per launch as dsmc_step / dsmc_group_step enqueue (in launches of up
+ * to 4096 steps), instead of six kernels per step.  Results are identical
+ * bit for bit either way; enable = 0 keeps the multi-kernel step.  Under
+ * dsmc_profile_step a resident lane's step appears as one kernel in the
+ * collide slot, and its other slots read 0.  INVALID_ARG unless enable is 0
+ * or 1. */
+int dsmc_group_set_resident(dsmc_group *g, int32_t enable);
 /* Time every pair of tile_mult in {1, 2, 4} and particles_per_block in
  * {0, 1024, 4096} on the group's own steps (4 steps each; they are real
  * steps of the members) and keep the fastest.  The choice is cached per group

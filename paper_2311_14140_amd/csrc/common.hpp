@@ -22,6 +22,8 @@ constexpr int kCoopMin = 256;          // cells this full are collided by a whol
 constexpr int kGroupTableFactor = 8;   // claim-table entries per lane of a small-cell group
 constexpr int kCoopTable = kFastWaves * kClaimTable;  // its claim table (the wave tables together)
 constexpr int kMaxCellsPerKey = 128;   // cells of one sort bucket (a power of two up to this)
+constexpr int kResidentKeys = 256;     // sort keys of an instance stepped by one workgroup
+constexpr int kResidentWaves = 16;     // wavefronts of that workgroup
 // records per lane the move-scatter holds in registers (FP32, FP64): tiles of
 // bucket-sorted instances are 256 times this many slots
 constexpr int kScatterRegs32 = 5, kScatterRegs64 = 4;

@@ -123,10 +123,11 @@ __global__ void k_init(const InstDesc* __restrict__ descs) {
 // the ordinary move delivers it with the drawn velocity at the boundary.
 
 // Injections of the coming step of an open instance holding `live`
-// particles, the remainder carried past it, and whether the slots ran out.
-__device__ __forceinline__ int injections(const InstDesc& d, int live, double& rem_next,
-                                          bool& clipped) {
-    const double m = d.os->inj_expected + d.os->inj_rem;
+// particles with `rem` carried from the earlier steps, the remainder carried
+// past it, and whether the slots ran out.
+__device__ __forceinline__ int injections(const InstDesc& d, int live, double rem,
+                                          double& rem_next, bool& clipped) {
+    const double m = d.os->inj_expected + rem;
     const double f = floor(m);
     rem_next = m - f;
     int64_t n = (int64_t)f;
@@ -304,7 +305,7 @@ template <bool kOpen> __device__ __forceinline__ Slots slots_before_scan(const I
     const int live = d.os->n_live;
     double rem;
     bool clipped;
-    return Slots{live, live + injections(d, live, rem, clipped)};
+    return Slots{live, live + injections(d, live, d.os->inj_rem, rem, clipped)};
 }
 template <bool kOpen> __device__ __forceinline__ int slots_after_scan(const InstDesc& d) {
     return (kOpen && d.open) ? d.os->n_used : d.N;
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
                 const int live = os->n_live;
                 double rem;
                 bool clipped;
-                const int n = injections(d, live, rem, clipped);
+                const int n = injections(d, live, os->inj_rem, rem, clipped);
                 if (clipped) atomicOr(&d.sc->status, 8);
                 os->inj_rem = rem;
                 os->n_injected += n;
@@ -1404,14 +1405,16 @@ __device__ __forceinline__ void halve(double* r, int off, bool upper, int& first
 // groups of a wavefront run in lockstep, so a round needs no barrier.  Cell
 // c of [c0, c1) holds lcnt[c - c0] particles from index loff[c - c0] of the
 // velocity arrays; lcrm / lrem hold copies of its crmax and remainder, read
-// before the sort so that their latency hides behind it.  Each cell has one
-// writer, so its counters and accumulators are updated with atomics that
-// return nothing (the same sums as a read-modify-write, without the wait).
+// before the sort so that their latency hides behind it; the new values go
+// to orem[c - c0] and ocrm[c - c0].  Each cell has one writer, so its
+// counters and accumulators are updated with atomics that return nothing
+// (the same sums as a read-modify-write, without the wait).
 template <class R, class V>
 __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c0, int c1,
                                             const int* lcnt, const int* loff, const double* lcrm,
                                             const double* lrem, V vx, V vy, V vz,
-                                            uint32_t* wtab, int G, bool do_collide, bool sample) {
+                                            uint32_t* wtab, int G, bool do_collide, bool sample,
+                                            double* orem, double* ocrm) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int ngw = 64 / G;
     const int grp = lane / G;
@@ -1495,8 +1498,8 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
         }
         const int gl = lane & (G - 1);
         if (has && gl == 0 && do_collide && nc >= 2) {
-            d.rem[c] = mreal - mf;
-            if (mx > crm0) d.crmax[c] = mx;
+            orem[c - c0] = mreal - mf;
+            if (mx > crm0) ocrm[c - c0] = mx;
             if (cc) atomicAdd(&d.ncoll[c], cc);
         }
         if (sample) {
@@ -1735,7 +1738,7 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
         for (int i = threadIdx.x; i < kClaims; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
         __syncthreads();
         group_cells<R, R*>(d, (uint32_t)s, c0, c1, lcnt, loff, lcrm, lrem, sx, sv, sz, wtab, G,
-                           do_collide, sample);
+                           do_collide, sample, d.rem + c0, d.crmax + c0);
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             g.vx[s0 + i] = sx[i];
@@ -1749,7 +1752,7 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_bucket(const InstDe
         for (int i = threadIdx.x; i < kClaims; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
         __syncthreads();
         group_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, lcnt, loff, lcrm, lrem, sx, sv, sz, wtab, G,
-                                do_collide, sample);
+                                do_collide, sample, d.rem + c0, d.crmax + c0);
         __syncthreads();
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             g.y[s0 + i] = sy[i];
@@ -1836,6 +1839,226 @@ __device__ void finalize_into(const InstDesc& d, double* est, double* col,
     }
 }
 
+// ----------------------------------------------- resident small instances
+// A small instance can run whole steps in one workgroup with its particles
+// held in LDS: no global sort, no launch per phase, and as many steps per
+// launch as asked.  Small means a fast mode, small cells (the bucket
+// collide's shape), at most kResidentKeys sort keys (its cells, and for an
+// open instance the key of the particles that left) and at most 4096 slots
+// in FP32 (2048 in FP64), ResidentRegs per lane.  Each step is the
+// multi-kernel step's arithmetic
+// in the same order: the injections of an open instance are drawn into the
+// slots after the live ones, slot i is flown with its wall stream (step, i)
+// and ranked in slot order by cell (the particles that left after every
+// cell), and the cells are collided and sampled bucket by bucket by
+// group_cells with the multi-kernel launch's lanes per cell G.  Both paths
+// therefore leave the same state bit for bit.  At the end of the launch the
+// particles, cell tables, step counters and boundary state go back to global
+// memory as the multi-kernel step leaves them.
+template <class R> struct ResidentRegs {
+    static constexpr int value = (sizeof(R) == 4 ? 4096 : 2048) / (64 * kResidentWaves);
+};
+static_assert(kResidentKeys <= 64 * kResidentWaves, "one key per thread of the resident workgroup");
+
+template <class R, bool kOpen>
+__global__ __launch_bounds__(64 * kResidentWaves) void k_resident(const InstDesc* __restrict__ descs,
+                                                                 const int2* __restrict__ work,
+                                                                 int64_t n_steps, int slot_cap) {
+    constexpr int W = kResidentWaves;
+    constexpr int K = ResidentRegs<R>::value;
+    constexpr int kClaims = W * 64 * kGroupTableFactor;
+    constexpr int kKeys = kResidentKeys;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* claims = (uint32_t*)smem;            // claim tables of the cell groups
+    int* wt = (int*)(claims + kClaims);            // per wavefront: keys counted, then ranks
+    int* lcnt = wt + W * kKeys;                    // particles per key
+    int* loff = lcnt + kKeys;                      // first slot of each key
+    double* lcrm = (double*)(loff + kKeys);        // crmax per cell
+    double* lrem = lcrm + kKeys;                   // NTC remainder per cell
+    R* ly = (R*)(lrem + kKeys);                    // the particles, slot order
+    R* lx = ly + slot_cap;
+    R* lv = lx + slot_cap;
+    R* lz = lv + slot_cap;
+    __shared__ int sh_live, sh_bad, wsum[W];
+    __shared__ double sh_rem;
+    __shared__ long long sh_inj, sh_del;
+    const int2 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int G = w.y;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int Cc = d.Cc;
+    const bool open = kOpen && d.open;
+    const int nk = Cc + (open ? 1 : 0);
+    int64_t s = d.sc->step_done;
+    {
+        const int live0 = open ? d.os->n_live : d.N;
+        const P4<R> src = particles<R>(d, (int)(s & 1));
+        for (int i = tid; i < live0; i += blockDim.x) {
+            ly[i] = src.y[i];
+            lx[i] = src.vx[i];
+            lv[i] = src.vy[i];
+            lz[i] = src.vz[i];
+        }
+        for (int c = tid; c < Cc; c += blockDim.x) {
+            lcrm[c] = d.crmax[c];
+            lrem[c] = d.rem[c];
+        }
+        for (int i = tid; i < kClaims; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
+        if (tid == 0) {
+            sh_live = live0;
+            sh_bad = 0;
+            if (open) {
+                sh_rem = d.os->inj_rem;
+                sh_inj = d.os->n_injected;
+                sh_del = d.os->n_deleted;
+            }
+        }
+    }
+    __syncthreads();
+    const int cpk = 1 << d.key_shift;
+    const int nbits = nk > 1 ? 32 - __builtin_clz((unsigned)(nk - 1)) : 0;
+    const unsigned long long lt = lanes_below(lane);
+    int* mine = wt + wv * kKeys;
+    uint32_t* wtab = claims + wv * 64 * kGroupTableFactor;
+    int64_t sampled = 0;
+    int used = sh_live;
+    for (int64_t t = 0; t < n_steps; ++t) {
+        ++s;
+        const int live = sh_live;
+        used = live;
+        double rem_next = 0.0;
+        bool clipped = false;
+        if (open) {
+            used = live + injections(d, live, sh_rem, rem_next, clipped);
+            for (int i = live + tid; i < used; i += blockDim.x)
+                inject_state<R>(d, (uint32_t)s, i - live, ly[i], lx[i], lv[i], lz[i]);
+        }
+        for (int k = tid; k < W * kKeys; k += blockDim.x) wt[k] = 0;
+        __syncthreads();
+        if (tid == 0 && open) {
+            sh_rem = rem_next;
+            sh_inj += used - live;
+            if (clipped) atomicOr(&sh_bad, 8);
+        }
+        // move: each wavefront takes a contiguous share of the slots and
+        // counts its keys
+        const int quarter = ((used + W - 1) / W + 63) / 64 * 64;
+        const int q0 = min(wv * quarter, used), q1 = min(q0 + quarter, used);
+        R ry[K], rx[K], rv[K], rz[K];
+        int key[K];
+        int bad = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = q0 + 64 * k + lane;
+            ry[k] = rx[k] = rv[k] = rz[k] = R(0);
+            key[k] = 0;
+            if (i < q1) {
+                ry[k] = ly[i];
+                rx[k] = lx[i];
+                rv[k] = lv[i];
+                rz[k] = lz[i];
+                bool gone = false;
+                move_one<R, kOpen>(d, (uint32_t)s, (uint32_t)i, ry[k], rx[k], rv[k], rz[k], gone);
+                bad |= !(isfinite(rx[k]) && isfinite(rv[k]) && isfinite(rz[k]));
+                key[k] = (kOpen && gone) ? Cc : cell_of<R>(d, ry[k]);
+                atomicAdd(&mine[key[k]], 1);
+            }
+        }
+        if (bad) atomicOr(&sh_bad, 1);
+        __syncthreads();
+        // keys' totals and first slots, and each wavefront's first slot per key
+        {
+            const int c = tid;
+            int tot = 0;
+            if (c < nk)
+                for (int q = 0; q < W; ++q) tot += wt[q * kKeys + c];
+            const int incl = wave_incl_scan(tot, lane);
+            if (lane == 63) wsum[wv] = incl;
+            __syncthreads();
+            int run = incl - tot;
+            for (int q = 0; q < wv; ++q) run += wsum[q];
+            if (c < nk) {
+                lcnt[c] = tot;
+                loff[c] = run;
+                for (int q = 0; q < W; ++q) {
+                    const int v = wt[q * kKeys + c];
+                    wt[q * kKeys + c] = run;
+                    run += v;
+                }
+                if (c == nk - 1 && run != used) atomicOr(&sh_bad, 2);
+            }
+        }
+        __syncthreads();
+        // stable rank in slot order, written back in place (every slot of the
+        // step is in registers)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (q0 + 64 * k < q1) {  // uniform over the wavefront
+                const bool valid = q0 + 64 * k + lane < q1;
+                unsigned long long m = __ballot(valid);
+                for (int b = 0; b < nbits; ++b) {
+                    const bool bit = (key[k] >> b) & 1;
+                    const unsigned long long bal = __ballot(bit);
+                    m &= bit ? bal : ~bal;
+                }
+                if (valid) {
+                    int pos = mine[key[k]] + __popcll(m & lt);
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    if ((m & lt) == 0ull) mine[key[k]] = pos + __popcll(m);
+                    if (pos < 0 || pos >= used) {
+                        atomicOr(&sh_bad, 4);
+                        pos = pos < 0 ? 0 : used - 1;
+                    }
+                    ly[pos] = ry[k];
+                    lx[pos] = rx[k];
+                    lv[pos] = rv[k];
+                    lz[pos] = rz[k];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+        if (tid == 0 && open) {
+            sh_live = loff[Cc];
+            sh_del += lcnt[Cc];
+        }
+        // collisions and sampling, bucket by bucket as the bucket collide
+        const bool sample = s > d.n_transient;
+        for (int c0 = 0; c0 < Cc; c0 += cpk)
+            group_cells<R, R*>(d, (uint32_t)s, c0, min(c0 + cpk, Cc), lcnt + c0, loff + c0, lcrm + c0,
+                               lrem + c0, lx, lv, lz, wtab, G, true, sample, lrem + c0, lcrm + c0);
+        if (sample) ++sampled;
+        __syncthreads();
+    }
+    const int live = sh_live;
+    const P4<R> dst = particles<R>(d, (int)(s & 1));
+    for (int i = tid; i < live; i += blockDim.x) {
+        dst.y[i] = ly[i];
+        dst.vx[i] = lx[i];
+        dst.vy[i] = lv[i];
+        dst.vz[i] = lz[i];
+    }
+    for (int c = tid; c < Cc; c += blockDim.x) {
+        d.crmax[c] = lcrm[c];
+        d.rem[c] = lrem[c];
+        d.count[c] = lcnt[c];
+        d.offset[c] = loff[c];
+    }
+    if (tid == 0) {
+        d.sc->step_done = s;
+        d.sc->n_sampled += sampled;
+        if (sh_bad) atomicOr(&d.sc->status, sh_bad);
+        if (open) {
+            d.os->n_live = live;
+            d.os->n_used = used;
+            d.os->inj_rem = sh_rem;
+            d.os->n_injected = sh_inj;
+            d.os->n_deleted = sh_del;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_finalize(const InstDesc* __restrict__ descs) {
     __shared__ double col[kFinalizeChunk];
     __shared__ unsigned long long coll_part[256];
@@ -1901,11 +2124,30 @@ void step_kernels_debug(const Work& w, Mode mode, unsigned phase, hipStream_t st
 }
 
 template <class R>
+void resident_kernel(const Work& w, Mode mode, int64_t n_steps, hipStream_t st) {
+    const size_t lds = resident_lds_bytes(mode, w.resident_cap);
+    if (w.has_open)
+        hipLaunchKernelGGL((k_resident<R, true>), dim3(w.n_resident), dim3(64 * kResidentWaves), lds, st,
+                           w.desc, w.resident, n_steps, w.resident_cap);
+    else
+        hipLaunchKernelGGL((k_resident<R, false>), dim3(w.n_resident), dim3(64 * kResidentWaves), lds, st,
+                           w.desc, w.resident, n_steps, w.resident_cap);
+}
+
+template <class R>
 void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipEvent_t* ev = nullptr) {
     const size_t hist_lds = (size_t)w.max_cc * sizeof(int);
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
+    if (w.n_resident) {
+        // a resident lane's step is one kernel: it is timed in the collide
+        // slot, and the other slots' events are not recorded
+        mark(5);
+        resident_kernel<R>(w, mode, 1, st);
+        mark(6);
+        return;
+    }
     mark(0);
     if ((phase & kPhaseMove) && (phase & kPhaseSort)) {
         if (w.has_open) {
@@ -1954,6 +2196,24 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
 }
 
 }  // namespace
+
+int resident_slots(Mode mode) {
+    return 64 * kResidentWaves * (mode == kFp32Fast ? ResidentRegs<float>::value : ResidentRegs<double>::value);
+}
+
+size_t resident_lds_bytes(Mode mode, int slot_cap) {
+    const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
+    return (size_t)kResidentWaves * 64 * kGroupTableFactor * sizeof(uint32_t) +
+           (size_t)(kResidentWaves + 2) * kResidentKeys * sizeof(int) +
+           (size_t)2 * kResidentKeys * sizeof(double) + (size_t)4 * slot_cap * rb;
+}
+
+void launch_resident(const Work& w, Mode mode, int64_t n_steps, hipStream_t s) {
+    if (mode == kFp32Fast)
+        resident_kernel<float>(w, mode, n_steps, s);
+    else
+        resident_kernel<double>(w, mode, n_steps, s);
+}
 
 size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max) {
     const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
@@ -2014,6 +2274,17 @@ hipError_t configure_kernels(size_t max_dynamic_lds) {
     set((const void*)k_move_scatter<double, false>);
     set((const void*)k_move_scatter<float, true>);
     set((const void*)k_move_scatter<double, true>);
+    return e;
+}
+
+hipError_t configure_resident(size_t max_dynamic_lds) {
+    const int bytes = (int)max_dynamic_lds;
+    hipError_t e = hipSuccess;
+    for (const void* f : {(const void*)k_resident<float, false>, (const void*)k_resident<float, true>,
+                          (const void*)k_resident<double, false>, (const void*)k_resident<double, true>}) {
+        const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (r != hipSuccess) e = r;
+    }
     return e;
 }
 

@@ -26,6 +26,11 @@ struct Work {
     int stage_max;          // tiles of at most this many slots are staged in LDS by the scatter
     int fast_cap;           // particles a fast-collide workgroup stages in LDS
     int has_open;           // some instance has an open boundary (open-boundary kernel variants)
+    // resident lanes (every member small): (instance, G) per workgroup of
+    // k_resident, which then runs whole steps instead of the lists above
+    const int2* resident;
+    int n_resident;
+    int resident_cap;       // particle slots each resident workgroup holds in LDS
 };
 
 void launch_init(const InstDesc& d, const InstDesc* d_desc, Mode mode, hipStream_t s);
@@ -35,6 +40,11 @@ void launch_step(const Work& w, Mode mode, unsigned phase, hipStream_t s);
 // after the last (ev must hold 7 events); the kernel order is the one of
 // dsmc_profile_step.
 void launch_step_timed(const Work& w, Mode mode, unsigned phase, hipStream_t s, hipEvent_t* ev);
+// n_steps whole steps of a resident lane in one launch.
+void launch_resident(const Work& w, Mode mode, int64_t n_steps, hipStream_t s);
+// Particle slots an instance may hold to be stepped by one workgroup.
+int resident_slots(Mode mode);
+size_t resident_lds_bytes(Mode mode, int slot_cap);
 void launch_finalize(const InstDesc* d_desc, int n_inst, hipStream_t s);
 // Estimators of n_inst instances into stage: instance b at d_off[b], its
 // kEstPerCell * C + 3 values followed by its status word.
@@ -46,5 +56,7 @@ size_t bucket_collide_lds_bytes(Mode mode, int cap);
 size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max);
 // Allow dynamic LDS up to max_dynamic_lds bytes for the kernels that use it.
 hipError_t configure_kernels(size_t max_dynamic_lds);
+// The same for the resident kernel, which may take most of a CU's LDS.
+hipError_t configure_resident(size_t max_dynamic_lds);
 
 }  // namespace dsmc

@@ -229,6 +229,30 @@ int device_max_lds() {
     return cached;
 }
 
+// Largest dynamic LDS of the resident kernel: the device's per-block limit
+// less room for its static shared variables, else 64 KiB.
+int resident_max_lds() {
+    static int cached = -1;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cached < 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        (void)hipGetLastError();
+        cached = 65536;
+        if (v - 1024 > 65536 && dsmc::configure_resident((size_t)(v - 1024)) == hipSuccess)
+            cached = v - 1024;
+        else
+            (void)dsmc::configure_resident((size_t)cached);
+        (void)hipGetLastError();
+        if (std::getenv("DSMC_VERBOSE"))
+            std::fprintf(stderr, "dsmc: resident kernel LDS limit %d\n", cached);
+    }
+    return cached;
+}
+
 }  // namespace
 
 struct dsmc_group;
@@ -295,6 +319,7 @@ struct dsmc_group {
     bool dirty = true;
     int tile_mult = 0;   // 0 = automatic
     int ppb = 0;         // target particles per fast-collide workgroup, 0 = automatic
+    bool resident = true;  // lanes of small instances step them in one workgroup each
     unsigned phase = DSMC_PHASE_ALL;
     int n_lanes = 1;     // lanes in use (lanes.size() may be larger)
     std::vector<Lane> lanes;
@@ -317,6 +342,7 @@ struct dsmc_group {
 namespace {
 
 constexpr int kGraphSteps = 8;
+constexpr int64_t kResidentChunk = 4096;  // steps per launch of a resident lane
 
 hipStream_t stream_of(const dsmc_handle* h) {
     return h->group ? h->group->stream : h->stream;
@@ -415,6 +441,11 @@ int build_lane(dsmc_group* g, Lane& lane) {
     int max_cc = 1;
     int cap = 64, group_cap = 64;
     int has_open = 0;
+    // the lane is resident if every member is small (fast mode, bucket
+    // collide shape, few keys, slots within one workgroup's registers)
+    std::vector<int2> resident;
+    bool all_small = g->resident && g->mode != kFp64Det && g->phase == DSMC_PHASE_ALL && n > 0;
+    int resident_cap = 64;
     for (int i = 0; i < n; ++i) {
         dsmc_handle* h = lane.members[i];
         InstDesc d = h->desc;
@@ -463,7 +494,14 @@ int build_lane(dsmc_group* g, Lane& lane) {
             for (int b = 0; b < d.nkeys - d.open; ++b) gblocks.push_back(make_int4(i, b, G, 0));
             const double per_block = per_cell * cpk;
             group_cap = std::max(group_cap, (int)std::ceil(per_block + 4.0 * std::sqrt(per_block) + 32.0));
+            if (d.Cc + d.open <= kResidentKeys && d.ncap <= resident_slots((Mode)g->mode)) {
+                resident.push_back(make_int2(i, G));
+                resident_cap = std::max(resident_cap, (d.ncap + 63) / 64 * 64);
+            } else {
+                all_small = false;
+            }
         } else {
+            all_small = false;
             const int cpb = auto_cpb(h, g->ppb);
             for (int c = 0; c < d.Cc; c += cpb) cblocks.push_back(make_int4(i, c, std::min(c + cpb, d.Cc), 0));
             // staging room for a block's particles: mean + 4 Poisson sigma
@@ -492,11 +530,13 @@ int build_lane(dsmc_group* g, Lane& lane) {
     for (const InstDesc& d : descs) any_staged |= d.tile_items <= stage_max;
     if (!any_staged || scatter_lds_bytes((Mode)g->mode, max_cc, stage_max) > (size_t)max_lds)
         stage_max = 0;
+    if (!all_small || resident_lds_bytes((Mode)g->mode, resident_cap) > (size_t)resident_max_lds())
+        resident.clear();
 
     auto bytes_of = [](size_t k, size_t sz) { return align_up(sz * std::max<size_t>(k, 1)); };
     const size_t need = bytes_of(n, sizeof(InstDesc)) + bytes_of(tiles.size(), sizeof(int2)) +
                         bytes_of(cols.size(), sizeof(int4)) + bytes_of(cblocks.size(), sizeof(int4)) +
-                        bytes_of(gblocks.size(), sizeof(int4));
+                        bytes_of(gblocks.size(), sizeof(int4)) + bytes_of(resident.size(), sizeof(int2));
     if (need > lane.d_bytes) {
         if (lane.d_mem) (void)hipFree(lane.d_mem);
         lane.d_mem = nullptr;
@@ -515,11 +555,14 @@ int build_lane(dsmc_group* g, Lane& lane) {
     int4* d_cb = (int4*)(base + o);
     o += bytes_of(cblocks.size(), sizeof(int4));
     int4* d_lb = (int4*)(base + o);
+    o += bytes_of(gblocks.size(), sizeof(int4));
+    int2* d_res = (int2*)(base + o);
     if (n) HIP_TRY(&g->err, hipMemcpy(d_desc, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
     if (!tiles.empty()) HIP_TRY(&g->err, hipMemcpy(d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice));
     if (!cols.empty()) HIP_TRY(&g->err, hipMemcpy(d_cols, cols.data(), sizeof(int4) * cols.size(), hipMemcpyHostToDevice));
     if (!cblocks.empty()) HIP_TRY(&g->err, hipMemcpy(d_cb, cblocks.data(), sizeof(int4) * cblocks.size(), hipMemcpyHostToDevice));
     if (!gblocks.empty()) HIP_TRY(&g->err, hipMemcpy(d_lb, gblocks.data(), sizeof(int4) * gblocks.size(), hipMemcpyHostToDevice));
+    if (!resident.empty()) HIP_TRY(&g->err, hipMemcpy(d_res, resident.data(), sizeof(int2) * resident.size(), hipMemcpyHostToDevice));
     Work& w = lane.work;
     w.desc = d_desc;
     w.n_inst = n;
@@ -536,6 +579,9 @@ int build_lane(dsmc_group* g, Lane& lane) {
     w.stage_max = stage_max;
     w.fast_cap = cap;
     w.has_open = has_open;
+    w.resident = d_res;
+    w.n_resident = (int)resident.size();
+    w.resident_cap = resident_cap;
     return DSMC_OK;
 }
 
@@ -570,13 +616,13 @@ int rebuild(dsmc_group* g) {
         g->lanes[k].members.push_back(h);
         load[k] += h->plan.N;
     }
+    g->phase = (g->solo && g->members.size() == 1 && g->members[0]->p.debug_phase_mask)
+                   ? g->members[0]->p.debug_phase_mask
+                   : (unsigned)DSMC_PHASE_ALL;
     for (int k = 0; k < nl; ++k) {
         const int r = build_lane(g, g->lanes[k]);
         if (r) return r;
     }
-    g->phase = (g->solo && g->members.size() == 1 && g->members[0]->p.debug_phase_mask)
-                   ? g->members[0]->p.debug_phase_mask
-                   : (unsigned)DSMC_PHASE_ALL;
     g->dirty = false;
     return DSMC_OK;
 }
@@ -596,6 +642,12 @@ int enqueue_steps(dsmc_group* g, int64_t n_steps) {
         const hipStream_t st = lane_stream(g, l);
         if (nl > 1) HIP_TRY(&g->err, hipStreamWaitEvent(st, g->fork, 0));
         int64_t left = n_steps;
+        if (l.work.n_resident) {
+            // whole steps in one launch per chunk
+            for (int64_t k = 0; k < n_steps; k += kResidentChunk)
+                launch_resident(l.work, mode, std::min<int64_t>(kResidentChunk, n_steps - k), st);
+            left = 0;
+        }
         if (left >= kGraphSteps && g->phase == DSMC_PHASE_ALL) {
             if (!l.gexec) {
                 if (!l.cap_stream) HIP_TRY(&g->err, hipStreamCreateWithFlags(&l.cap_stream, hipStreamNonBlocking));
@@ -1142,11 +1194,15 @@ int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
     }
     const auto t1 = std::chrono::steady_clock::now();
     if (rc == DSMC_OK) {
-        for (size_t b = 0; b < nblk; ++b)
-            for (int i = 0; i < 6; ++i) {
+        for (size_t b = 0; b < nblk; ++b) {
+            // a resident lane records only the events around its one kernel
+            const int first = g->lanes[b % nl].work.n_resident ? 5 : 0;
+            for (int i = first; i < 6; ++i) {
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, ev[7 * b + i], ev[7 * b + i + 1]) == hipSuccess) acc[i] += ms;
             }
+        }
+        (void)hipGetLastError();
     }
     for (auto e : ev)
         if (e) (void)hipEventDestroy(e);
@@ -1294,6 +1350,14 @@ int dsmc_group_set_tuning(dsmc_group* g, int32_t tile_mult, int32_t particles_pe
         return fail(&g->err, DSMC_ERR_INVALID_ARG, "tuning out of range");
     g->tile_mult = tile_mult;
     g->ppb = particles_per_block;
+    g->dirty = true;
+    return DSMC_OK;
+}
+
+int dsmc_group_set_resident(dsmc_group* g, int32_t enable) {
+    if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
+    if (enable != 0 && enable != 1) return fail(&g->err, DSMC_ERR_INVALID_ARG, "enable must be 0 or 1");
+    g->resident = enable != 0;
     g->dirty = true;
     return DSMC_OK;
 }

@@ -36,6 +36,7 @@ EXPORTS = (
     "dsmc_set_cells", "dsmc_info", "dsmc_status_string", "dsmc_last_error",
     "dsmc_group_create", "dsmc_group_add", "dsmc_group_remove", "dsmc_group_step",
     "dsmc_group_sync", "dsmc_group_size", "dsmc_group_lanes", "dsmc_group_destroy", "dsmc_group_set_tuning",
+    "dsmc_group_set_resident",
     "dsmc_group_autotune", "dsmc_profile_step", "dsmc_group_sample", "dsmc_set_inflow",
     "dsmc_open_state", "dsmc_set_open_state",
 )
@@ -100,6 +101,7 @@ def _load():
         "dsmc_set_open_state": [vp, i32, i64, i64, ct.c_double],
         "dsmc_group_destroy": [vp],
         "dsmc_group_set_tuning": [vp, i32, i32],
+        "dsmc_group_set_resident": [vp, i32],
         "dsmc_group_autotune": [vp, ct.POINTER(i32), ct.POINTER(i32)],
         "dsmc_profile_step": [vp, i64, vp],
     }
@@ -372,6 +374,11 @@ class Group:
 
     def set_tuning(self, tile_mult: int = 0, particles_per_block: int = 0):
         _check(lib.dsmc_group_set_tuning(self._g, int(tile_mult), int(particles_per_block)))
+
+    def set_resident(self, enable: bool = True):
+        """Step small members in one workgroup each (the default) or with the
+        multi-kernel step; the results are the same."""
+        _check(lib.dsmc_group_set_resident(self._g, 1 if enable else 0))
 
     def autotune(self):
         a, b = ct.c_int32(), ct.c_int32()

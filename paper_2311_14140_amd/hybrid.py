@@ -176,12 +176,15 @@ def hybrid(kn: float, force: float | None = None, iterations: int = 16,
 def time_patch_group(kn: float, open_boundary: bool = True, replicas: int = 64,
                      steps: int = 2000, profile_steps: int = 50, dy: float = 0.005,
                      particles_per_cell: int = 50, u_in: float = 0.03,
-                     dudy_in: float = 0.07) -> dict:
+                     dudy_in: float = 0.07, resident: bool = True) -> dict:
     """Cost of one step of the hybrid's DSMC: ``replicas`` patches at ``kn``
     (FP32) batched in one group, with their open boundary and a fixed inflow,
-    or closed at the same size for comparison.  Wall time per step over
-    ``steps`` graph-replayed steps, and device time per kernel slot from
-    ``profile_steps`` eagerly launched steps timed with HIP events."""
+    or closed at the same size for comparison; resident (one workgroup per
+    patch, whole steps per launch) where the patches are small enough, or
+    with the multi-kernel step.  Wall time per step over ``steps`` steps, and
+    device time per kernel slot from ``profile_steps`` eagerly launched steps
+    timed with HIP events (a resident step is one kernel, in the collide
+    slot)."""
     import synth
     from . import dsmc
     patch = patch_for(kn, dy)
@@ -195,6 +198,7 @@ def time_patch_group(kn: float, open_boundary: bool = True, replicas: int = 64,
     try:
         solvers = [dsmc.Solver(p) for p in ps]
         group = dsmc.Group()
+        group.set_resident(resident)
         for s in solvers:
             if open_boundary:
                 s.set_inflow(u=u_in, dudy=dudy_in)
@@ -212,7 +216,8 @@ def time_patch_group(kn: float, open_boundary: bool = True, replicas: int = 64,
             group.close()
         for s in solvers:
             s.close()
-    return dict(kn=kn, open=open_boundary, replicas=replicas, patch_cells=patch.n_cells,
+    return dict(kn=kn, open=open_boundary, resident=resident, replicas=replicas,
+                patch_cells=patch.n_cells,
                 particles=live, ms_per_step=wall * 1e3, particle_steps_per_s=live / wall,
                 kernel_ms_per_step={k: prof[k] / profile_steps for k in dsmc.Solver.PHASES})
 
@@ -228,13 +233,15 @@ def main():
     ap.add_argument("--bench-replicas", type=int, default=8)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--time-patches", action="store_true",
-                    help="only time the patch group per step, open and closed, at each Kn")
+                    help="only time the patch group per step at each Kn: open and closed, "
+                         "resident and multi-kernel")
     a = ap.parse_args()
     if a.time_patches:
         for kn in a.kn:
             for open_boundary in (True, False):
-                print(json.dumps(time_patch_group(kn, open_boundary, replicas=a.replicas)),
-                      flush=True)
+                for resident in (True, False):
+                    print(json.dumps(time_patch_group(kn, open_boundary, replicas=a.replicas,
+                                                      resident=resident)), flush=True)
         return
     import synth
     from .mms import compare_with_benchmark, run_benchmark
