@@ -290,7 +290,7 @@ int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t particles_pe
 /* Resident stepping of small instances (on by default).  When every member
  * of a lane is small -- a fast mode, fewer than 256 particles per collision
  * cell, at most 256 collision cells (255 for an open instance) and at most
- * 4096 particle slots in FP32 or 2048 in FP64_FAST -- the lane runs each
+ * 6144 particle slots in FP32 or 3072 in FP64_FAST -- the lane runs each
  * member in one workgroup that holds its particles in LDS and performs whole
  * steps (move, stable sort by cell, collisions, sampling) back to back, as
  * many per launch as dsmc_step / dsmc_group_step enqueue (in launches of up

@@ -1844,8 +1844,8 @@ __device__ void finalize_into(const InstDesc& d, double* est, double* col,
 // held in LDS: no global sort, no launch per phase, and as many steps per
 // launch as asked.  Small means a fast mode, small cells (the bucket
 // collide's shape), at most kResidentKeys sort keys (its cells, and for an
-// open instance the key of the particles that left) and at most 4096 slots
-// in FP32 (2048 in FP64), ResidentRegs per lane.  Each step is the
+// open instance the key of the particles that left) and at most 6144 slots
+// in FP32 (3072 in FP64), ResidentRegs per lane.  Each step is the
 // multi-kernel step's arithmetic
 // in the same order: the injections of an open instance are drawn into the
 // slots after the live ones, slot i is flown with its wall stream (step, i)
@@ -1856,7 +1856,7 @@ __device__ void finalize_into(const InstDesc& d, double* est, double* col,
 // particles, cell tables, step counters and boundary state go back to global
 // memory as the multi-kernel step leaves them.
 template <class R> struct ResidentRegs {
-    static constexpr int value = (sizeof(R) == 4 ? 4096 : 2048) / (64 * kResidentWaves);
+    static constexpr int value = (sizeof(R) == 4 ? 6144 : 3072) / (64 * kResidentWaves);
 };
 static_assert(kResidentKeys <= 64 * kResidentWaves, "one key per thread of the resident workgroup");
 

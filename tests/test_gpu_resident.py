@@ -35,6 +35,9 @@ CASES = [
                               particles_per_cell=50, domain_length=0.225), dict(u=0.0333, dudy=0.069)),
     ("open_patch_kn0.01", dict(kn=0.01, body_force=synth.training_force(0.01), n_cells=9,
                                particles_per_cell=50, domain_length=0.045), dict(u=0.004, dudy=0.02)),
+    ("open_patch_kn0.2", dict(kn=0.2, body_force=synth.training_force(0.2), n_cells=85,
+                              particles_per_cell=50, domain_length=0.425), dict(u=0.05, dudy=0.015)),
+    ("closed_kn0.2_60x48", dict(kn=0.2, body_force=0.01, n_cells=60, particles_per_cell=48), None),
 ]
 
 
@@ -91,7 +94,7 @@ def _assert_same(a, b):
 def test_resident_equals_multi_kernel(D, prec_name, name, kw, inflow):
     prec = getattr(D, prec_name)
     p = Params(seed=synth.seed_of(13, len(name)), n_transient=30, precision=prec, **kw)
-    if _slots(p) > (4096 if prec == D.DSMC_FP32_FAST else 2048):
+    if _slots(p) > (6144 if prec == D.DSMC_FP32_FAST else 3072):
         pytest.skip("more slots than one workgroup holds: stepped by the multi-kernel path")
     _say(f"resident vs multi-kernel: {name} {prec_name}")
     windows = (1, 36, 100)
