@@ -303,6 +303,16 @@ def main():
         extra["cfg2_large_instance"] = time_single(dsmc, torch, WORKLOADS["cfg2"][0].with_(n_sub=2),
                                                    max(2, args.extra_steps // 10), "cfg2")
         log(f"cfg2: {extra['cfg2_large_instance']['value']:.4e}")
+        from paper_2311_14140_amd.hybrid import time_patch_group
+        for resident in (True, False):
+            t = time_patch_group(0.1, True, replicas=64, steps=2000, profile_steps=4,
+                                 resident=resident)
+            key = "hybrid_patches_kn0.1_" + ("resident" if resident else "multi_kernel")
+            extra[key] = {"value": t["particle_steps_per_s"], "unit": "particle-steps/s",
+                          "particles": t["particles"], "ms_per_step": t["ms_per_step"],
+                          "workload": "64 open patches of the MMS hybrid at Kn 0.1 (45 cells x 50/cell, "
+                                      "Chapman-Enskog inflow), FP32, one group"}
+            log(f"{key}: {t['particle_steps_per_s']:.4e}")
         if args.serve_requests > 0:
             free, _ = torch.cuda.mem_get_info()
             budget = int(0.8 * free)
