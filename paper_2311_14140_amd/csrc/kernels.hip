@@ -1850,8 +1850,8 @@ __device__ void finalize_into(const InstDesc& d, double* est, double* col,
 // in the same order: the injections of an open instance are drawn into the
 // slots after the live ones, slot i is flown with its wall stream (step, i)
 // and ranked in slot order by cell (the particles that left after every
-// cell), and the cells are collided and sampled bucket by bucket by
-// group_cells with the multi-kernel launch's lanes per cell G.  Both paths
+// cell), and the cells are collided and sampled by group_cells with the
+// multi-kernel launch's lanes per cell G.  Both paths
 // therefore leave the same state bit for bit.  At the end of the launch the
 // particles, cell tables, step counters and boundary state go back to global
 // memory as the multi-kernel step leaves them.
@@ -1915,7 +1915,6 @@ __global__ __launch_bounds__(64 * kResidentWaves) void k_resident(const InstDesc
         }
     }
     __syncthreads();
-    const int cpk = 1 << d.key_shift;
     const int nbits = nk > 1 ? 32 - __builtin_clz((unsigned)(nk - 1)) : 0;
     const unsigned long long lt = lanes_below(lane);
     int* mine = wt + wv * kKeys;
@@ -2023,11 +2022,12 @@ __global__ __launch_bounds__(64 * kResidentWaves) void k_resident(const InstDesc
             sh_live = loff[Cc];
             sh_del += lcnt[Cc];
         }
-        // collisions and sampling, bucket by bucket as the bucket collide
+        // collisions and sampling of all cells at once, with the bucket
+        // collide's G (a cell's arithmetic does not depend on which group
+        // of which wavefront takes it)
         const bool sample = s > d.n_transient;
-        for (int c0 = 0; c0 < Cc; c0 += cpk)
-            group_cells<R, R*>(d, (uint32_t)s, c0, min(c0 + cpk, Cc), lcnt + c0, loff + c0, lcrm + c0,
-                               lrem + c0, lx, lv, lz, wtab, G, true, sample, lrem + c0, lcrm + c0);
+        group_cells<R, R*>(d, (uint32_t)s, 0, Cc, lcnt, loff, lcrm, lrem, lx, lv, lz, wtab, G, true,
+                           sample, lrem, lcrm);
         if (sample) ++sampled;
         __syncthreads();
     }
