@@ -139,3 +139,43 @@ def test_set_resident_argument_check(D):
     assert D.lib.dsmc_group_set_resident(g._g, 2) == D.DSMC_ERR_INVALID_ARG
     assert D.lib.dsmc_group_set_resident(None, 1) == D.DSMC_ERR_INVALID_ARG
     g.close()
+
+
+def test_two_resident_lanes_equal_alone(D):
+    """520 small instances (2.08e6 particles) run in two lanes, each of them
+    resident; members equal themselves stepped alone, also after the group is
+    autotuned (the autotune's steps use other bucket sizes, so other lanes
+    per cell: the states stay the same, the window sums may differ in the
+    last bits, and only the states are compared after it)."""
+    ps = [Params(kn=0.5 + 0.01 * (r % 7), body_force=0.01, n_cells=80, particles_per_cell=50,
+                 seed=synth.seed_of(15, r), n_transient=5, precision=D.DSMC_FP32_FAST)
+          for r in range(520)]
+    _say("520 small instances in two resident lanes")
+    sols = [D.Solver(p) for p in ps]
+    g = D.Group()
+    for s in sols:
+        g.add(s)
+    g.step(23)
+    g.sync()
+    assert g.lanes() == 2
+    prof = sols[0].profile(1)
+    assert prof["count"] == 0 and prof["collide"] > 0
+    picks = (0, 259, 519)
+    before = [(sols[i].get_state(), sols[i].sample(raw=True)["raw"]) for i in picks]
+    g.autotune()
+    g.sync()
+    after = [sols[i].get_state() for i in picks]
+    g.close()
+    for s in sols:
+        s.close()
+    for i, (st, raw), st2 in zip(picks, before, after):
+        with D.Solver(ps[i]) as s:
+            s.step(24)
+            s.sync()
+            for a, b in zip(s.get_state(), st):
+                assert np.array_equal(np.asarray(a), np.asarray(b))
+            assert np.array_equal(s.sample(raw=True)["raw"], raw)
+            s.step(int(st2[5]) - 24)
+            s.sync()
+            for a, b in zip(s.get_state(), st2):
+                assert np.array_equal(np.asarray(a), np.asarray(b))
