@@ -16,6 +16,7 @@ constexpr int kScatterWaves = kParticleThreads / 64;  // wavefronts of a scatter
 constexpr int kColThreads = 256;       // cells per workgroup of the column-scan kernels
 constexpr int kScanThreads = 1024;     // threads of the per-instance scan kernel
 constexpr int kSegTiles = 32;          // tiles per column-scan segment
+constexpr int kCountScanEntries = 8192;  // largest count matrix (tiles x keys) scanned in LDS
 constexpr int kClaimTable = 1024;      // per-wavefront claim table of the fast collide
 constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
 constexpr int kCoopMin = 256;          // cells this full are collided by a whole workgroup

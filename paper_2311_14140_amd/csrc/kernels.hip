@@ -389,6 +389,31 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 // scan of kcount in key order.  Also advances the instance's step counter
 // (and the sampled-step count).  The segment loads of a cell are independent,
 // so they are issued together.
+// Thread 0's bookkeeping of the step's injections at the scan of an open
+// instance (they were drawn by the count pass), before its live count is
+// replaced: their number and the remainder carried on.  Returns the slots in
+// use during the step (N when closed).
+__device__ __forceinline__ int book_injections(const InstDesc& d) {
+    if (!d.open) return d.N;
+    OpenState* os = d.os;
+    const int live = os->n_live;
+    double rem;
+    bool clipped;
+    const int n = injections(d, live, os->inj_rem, rem, clipped);
+    if (clipped) atomicOr(&d.sc->status, 8);
+    os->inj_rem = rem;
+    os->n_injected += n;
+    os->n_used = live + n;
+    return live + n;
+}
+
+// Thread 0: the instance's step counter (and the sampled-step count).
+__device__ __forceinline__ void advance_step(const InstDesc& d) {
+    const int64_t s = d.sc->step_done + 1;
+    d.sc->step_done = s;
+    if ((d.phase_mask & kPhaseSample) && s > d.n_transient) d.sc->n_sampled += 1;
+}
+
 __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restrict__ descs,
                                                      int do_scan) {
     const InstDesc& d = descs[blockIdx.x];
@@ -396,24 +421,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
     __shared__ int sh_used;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (do_scan) {
-        // an open instance's injections of this step (drawn by the particle
-        // passes) are booked here, before its live count is replaced below
-        if (tid == 0) {
-            int used = d.N;
-            if (d.open) {
-                OpenState* os = d.os;
-                const int live = os->n_live;
-                double rem;
-                bool clipped;
-                const int n = injections(d, live, os->inj_rem, rem, clipped);
-                if (clipped) atomicOr(&d.sc->status, 8);
-                os->inj_rem = rem;
-                os->n_injected += n;
-                used = live + n;
-                os->n_used = used;
-            }
-            sh_used = used;
-        }
+        if (tid == 0) sh_used = book_injections(d);
         __syncthreads();
         const int Cc = d.nkeys, nseg = d.nseg;
         const gptr<int32_t> seg = gmem(d.segsum);
@@ -466,11 +474,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
             atomicOr(&d.sc->status, 2);
     }
     __syncthreads();
-    if (tid == 0) {
-        const int64_t s = d.sc->step_done + 1;
-        d.sc->step_done = s;
-        if ((d.phase_mask & kPhaseSample) && s > d.n_transient) d.sc->n_sampled += 1;
-    }
+    if (tid == 0) advance_step(d);
 }
 
 // Per-tile scatter bases of a segment: koffset[c] + the prefix of the earlier
@@ -702,6 +706,58 @@ __global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __re
     __syncthreads();
     const gptr<int32_t> row = gmem(d.counts) + (size_t)w.y * nk;
     for (int c = threadIdx.x; c < nk; c += blockDim.x) row[c] = hist[c];
+}
+
+// The column scans in one workgroup per instance, for lanes whose instances
+// have small count matrices (tiles x keys within the LDS of one workgroup,
+// at most kScanThreads keys): the tile histograms of k_count are read into
+// LDS and scanned there, which gives the per-tile scatter bases, key counts
+// and offsets and the bookkeeping of k_colsum, k_scan and k_colprefix: one
+// launch instead of three.
+__global__ __launch_bounds__(kScanThreads) void k_scan_small(const InstDesc* __restrict__ descs) {
+    extern __shared__ int hist[];  // tiles x keys: counts, then prefixes over the tiles
+    __shared__ int wsum[kScanThreads / 64];
+    __shared__ int sh_used;
+    const InstDesc& d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nk = d.nkeys, T = d.tiles;
+    const gptr<int32_t> cnt = gmem(d.counts);
+    for (int i = tid; i < T * nk; i += blockDim.x) hist[i] = cnt[i];
+    if (tid == 0) sh_used = book_injections(d);
+    __syncthreads();
+    // key c = tid: exclusive prefix over the tiles and the key's total
+    const int c = tid;
+    int tot = 0;
+    if (c < nk)
+        for (int t = 0; t < T; ++t) {
+            const int v = hist[t * nk + c];
+            hist[t * nk + c] = tot;
+            tot += v;
+        }
+    const int incl = wave_incl_scan(tot, lane);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    if (wv == 0) {
+        int v = lane < kScanThreads / 64 ? wsum[lane] : 0;
+        v = wave_incl_scan(v, lane);
+        if (lane < kScanThreads / 64) wsum[lane] = v;
+    }
+    __syncthreads();
+    if (c < nk) {
+        const int off = incl - tot + (wv ? wsum[wv - 1] : 0);
+        d.kcount[c] = tot;
+        d.koffset[c] = off;
+        // an open instance's last key holds the particles that left: the
+        // live ones are those before it
+        if (d.open && c == nk - 1) {
+            d.os->n_live = off;
+            d.os->n_deleted += tot;
+        }
+        for (int t = 0; t < T; ++t) cnt[(size_t)t * nk + c] = off + hist[t * nk + c];
+    }
+    if (tid == kScanThreads - 1 && wsum[kScanThreads / 64 - 1] != sh_used) atomicOr(&d.sc->status, 2);
+    __syncthreads();
+    if (tid == 0) advance_step(d);
 }
 
 // Records per lane k_move_scatter holds in registers (tiles up to
@@ -2150,19 +2206,26 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
     }
     mark(0);
     if ((phase & kPhaseMove) && (phase & kPhaseSort)) {
-        if (w.has_open) {
+        if (w.has_open)
             hipLaunchKernelGGL((k_count<R, true>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds,
                                st, w.desc, w.tiles);
-        } else {
+        else
             hipLaunchKernelGGL((k_count<R, false>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds,
                                st, w.desc, w.tiles);
-        }
         mark(1);
-        hipLaunchKernelGGL(k_colsum, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
-        mark(2);
-        hipLaunchKernelGGL(k_scan, dim3(w.n_inst), dim3(kScanThreads), 0, st, w.desc, 1);
-        mark(3);
-        hipLaunchKernelGGL(k_colprefix, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
+        if (w.count_scan_lds) {
+            // the three column scans in one launch, in the scan slot
+            mark(2);
+            hipLaunchKernelGGL(k_scan_small, dim3(w.n_inst), dim3(kScanThreads),
+                               (size_t)w.count_scan_lds, st, w.desc);
+            mark(3);
+        } else {
+            hipLaunchKernelGGL(k_colsum, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
+            mark(2);
+            hipLaunchKernelGGL(k_scan, dim3(w.n_inst), dim3(kScanThreads), 0, st, w.desc, 1);
+            mark(3);
+            hipLaunchKernelGGL(k_colprefix, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
+        }
         mark(4);
         if (w.has_open)
             hipLaunchKernelGGL((k_move_scatter<R, true>), dim3(w.n_tiles), dim3(kParticleThreads),
@@ -2274,6 +2337,7 @@ hipError_t configure_kernels(size_t max_dynamic_lds) {
     set((const void*)k_move_scatter<double, false>);
     set((const void*)k_move_scatter<float, true>);
     set((const void*)k_move_scatter<double, true>);
+    set((const void*)k_scan_small);
     return e;
 }
 

@@ -532,6 +532,16 @@ int build_lane(dsmc_group* g, Lane& lane) {
         stage_max = 0;
     if (!all_small || resident_lds_bytes((Mode)g->mode, resident_cap) > (size_t)resident_max_lds())
         resident.clear();
+    // the column scans in one workgroup per instance when every count matrix is small
+    int count_scan_entries = 0;
+    bool small_counts = resident.empty() && n > 0 &&
+                        (g->phase & (DSMC_PHASE_MOVE | DSMC_PHASE_SORT)) == (DSMC_PHASE_MOVE | DSMC_PHASE_SORT);
+    for (const InstDesc& d : descs) {
+        const int64_t e = (int64_t)d.tiles * d.nkeys;
+        small_counts &= d.nkeys <= kScanThreads && e <= kCountScanEntries;
+        count_scan_entries = std::max<int>(count_scan_entries, (int)std::min<int64_t>(e, INT32_MAX));
+    }
+    const int count_scan_lds = small_counts ? std::max(count_scan_entries, 1) * (int)sizeof(int) : 0;
 
     auto bytes_of = [](size_t k, size_t sz) { return align_up(sz * std::max<size_t>(k, 1)); };
     const size_t need = bytes_of(n, sizeof(InstDesc)) + bytes_of(tiles.size(), sizeof(int2)) +
@@ -582,6 +592,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
     w.resident = d_res;
     w.n_resident = (int)resident.size();
     w.resident_cap = resident_cap;
+    w.count_scan_lds = count_scan_lds;
     return DSMC_OK;
 }
 
@@ -1195,9 +1206,12 @@ int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
     const auto t1 = std::chrono::steady_clock::now();
     if (rc == DSMC_OK) {
         for (size_t b = 0; b < nblk; ++b) {
-            // a resident lane records only the events around its one kernel
-            const int first = g->lanes[b % nl].work.n_resident ? 5 : 0;
-            for (int i = first; i < 6; ++i) {
+            // a resident lane records only the events around its one kernel,
+            // a lane with the single-kernel scan none around the column sums
+            // and prefixes
+            const Work& w = g->lanes[b % nl].work;
+            for (int i = 0; i < 6; ++i) {
+                if ((w.n_resident && i < 5) || (w.count_scan_lds && (i == 1 || i == 3))) continue;
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, ev[7 * b + i], ev[7 * b + i + 1]) == hipSuccess) acc[i] += ms;
             }
