@@ -2,19 +2,27 @@
 //
 // One step of force-driven parallel-plate DSMC (the micro model of arXiv
 // 2311.14140, Sec. 2.1: gas between isothermal plates under a body force
-// parallel to them) is five phases, each one launch over every instance of a
-// group:
-//   1. k_move_hist   free flight under the body force, diffuse wall
-//                    re-emission, collision-cell index, per-tile LDS histogram
-//   2. k_colsum      per-segment column sums of the tile histograms
-//   3. k_scan        per-instance exclusive scan: cell counts and offsets,
-//                    segment bases; advances the step counter
-//   4. k_colprefix   per-tile scatter bases (column prefix within a segment)
-//   5. k_scatter     stable scatter of the SoA records into cell order
-//   6. k_collide_*   NTC hard-sphere collisions per collision cell, fused with
-//                    the FP64 moment sums of the sampling steps
-// Everything is HBM-bound streaming over structure-of-arrays particle
-// records; there is no dense contraction anywhere, so no MFMA.
+// parallel to them) is these launches, each over every instance of a group
+// (of one lane of it):
+//   k_count         position-only flight of every slot (an open instance's
+//                   injections drawn first), per-tile LDS histogram of sort keys
+//   k_colsum        per-segment column sums of the tile histograms
+//   k_scan          per-instance exclusive scan: key counts and offsets,
+//                   segment bases; step counter and open-boundary bookkeeping
+//   k_colprefix     per-tile scatter bases (column prefix within a segment)
+//                   (k_scan_small does these three in one workgroup per
+//                   instance when every count matrix is small)
+//   k_move_scatter  the full move (force, diffuse walls, open boundary) and
+//                   the stable scatter of the SoA records into key order
+//   k_collide_*     NTC hard-sphere collisions per collision cell (the bucket
+//                   variant first finishes the sort by cell in LDS), fused
+//                   with the FP64 moment sums of the sampling steps
+// A lane of small instances runs k_resident instead: one workgroup per
+// instance performs whole steps with its particles held in LDS.  Debug phase
+// masks use k_move_hist, k_scatter and k_copy, which separate the move from
+// the sort.
+// Everything is streaming over structure-of-arrays particle records; there
+// is no dense contraction anywhere, so no MFMA.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
