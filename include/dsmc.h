@@ -297,7 +297,7 @@ int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t particles_pe
  * member in one workgroup that holds its particles in LDS and performs whole
  * steps (move, stable sort by cell, collisions, sampling) back to back, as
  * many per launch as dsmc_step / dsmc_group_step enqueue (in launches of up
- * to 4096 steps), instead of six kernels per step.  Results are identical
+ * to 4096 steps), instead of a launch per phase.  Results are identical
  * bit for bit either way; enable = 0 keeps the multi-kernel step.  Under
  * dsmc_profile_step a resident lane's step appears as one kernel in the
  * collide slot, and its other slots read 0.  INVALID_ARG unless enable is 0
