@@ -90,6 +90,13 @@ bool bucket_eligible(const dsmc_params* p) {
            (double)p->particles_per_cell / (double)p->n_sub < (double)kCoopMin;
 }
 
+// A small bucket-sorted instance gets 256-slot base tiles, so that a lane
+// of a few such instances can cut them fine enough to give the particle
+// kernels tens of workgroups; a lane with enough tiles groups them back into
+// full register tiles (kScatterRegs per thread).  Tiles never change results.
+constexpr int32_t kSmallInstance = 16384;
+constexpr int64_t kLaneTilesEnough = 2048;  // 256-slot tiles a lane needs to keep full tiles
+
 int check_params(const dsmc_params* p, std::string* err) {
     if (!p) return fail(err, DSMC_ERR_INVALID_ARG, "params is NULL");
     if (p->struct_size != sizeof(dsmc_params))
@@ -164,6 +171,7 @@ Plan make_plan(const dsmc_params* p) {
         // few sort keys: tiles as large as the move-scatter holds in registers
         const int regs = q.rb == 4 ? kScatterRegs32 : kScatterRegs64;
         k = std::max(1, std::min(regs, (q.N + kParticleThreads - 1) / kParticleThreads));
+        if (q.N <= kSmallInstance) k = 1;
     }
     q.tile_items = k * kParticleThreads;
     q.tiles = (q.ncap + q.tile_items - 1) / q.tile_items;
@@ -446,6 +454,10 @@ int build_lane(dsmc_group* g, Lane& lane) {
     std::vector<int2> resident;
     bool all_small = g->resident && g->mode != kFp64Det && g->phase == DSMC_PHASE_ALL && n > 0;
     int resident_cap = 64;
+    // a lane with few 256-slot tiles keeps its small instances' tiles fine
+    int64_t lane_tiles = 0;
+    for (const dsmc_handle* h : lane.members) lane_tiles += (h->plan.ncap + kParticleThreads - 1) / kParticleThreads;
+    const bool fine_tiles = lane_tiles < kLaneTilesEnough;
     for (int i = 0; i < n; ++i) {
         dsmc_handle* h = lane.members[i];
         InstDesc d = h->desc;
@@ -472,7 +484,9 @@ int build_lane(dsmc_group* g, Lane& lane) {
         has_open |= d.open;
         // launch shape: tiles may only grow (the histogram matrix is sized
         // for the base tile and all cells)
-        const int mult = g->tile_mult > 0 ? g->tile_mult : 1;
+        int mult = g->tile_mult > 0 ? g->tile_mult : 1;
+        if (g->tile_mult <= 0 && !fine_tiles && bucket_eligible(&h->p) && h->plan.N <= kSmallInstance)
+            mult = g->mode == kFp32Fast ? kScatterRegs32 : kScatterRegs64;
         const int64_t items = std::min<int64_t>(base_items * mult,
                                                 (int64_t)std::max(h->plan.ncap, 1) + kParticleThreads);
         d.tile_items = (int32_t)((items + kParticleThreads - 1) / kParticleThreads * kParticleThreads);

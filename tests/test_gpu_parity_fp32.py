@@ -348,18 +348,18 @@ def test_collide_global_fallback_equals_staged(D):
 def test_bucket_overflow_on_global_memory_equals_staged(D):
     """Small cells are sorted by buckets of cells, and each bucket is sorted
     by cell in LDS by its collide workgroup.  A crafted state puts every
-    particle in one cell: with the default buckets (64 cells here) that bucket
-    overflows the staging room and is sorted and collided in global memory;
-    with 8192-particle buckets the whole instance is one staged bucket.  The
-    states, per-cell tables and moments must be identical, and the state must
-    be sorted by cell."""
+    particle in one cell: with 2048-particle buckets (64 cells here) that
+    bucket overflows the staging room and is sorted and collided in global
+    memory; with 8192-particle buckets the whole instance is one staged
+    bucket.  Both give 4 lanes per cell, so the states, per-cell tables and
+    moments must be identical, and the state must be sorted by cell."""
     p = Params(kn=0.3, body_force=0.01, n_cells=250, particles_per_cell=24, seed=81,
                n_transient=0, precision=D.DSMC_FP32_FAST)
     rng = np.random.default_rng(9)
     y = (0.001 + 0.002 * rng.random(p.n_particles)).astype(np.float32)  # all in cell 0
     v = rng.normal(size=(3, p.n_particles)).astype(np.float32)
     out = []
-    for ppb in (0, 8192):
+    for ppb in (2048, 8192):
         g = D.Group()
         s = D.Solver(p)
         s.set_state(y, v[0], v[1], v[2], step=0)
@@ -390,8 +390,10 @@ def test_wall_reemission_paths_agree(D, prec_name):
     times per step: with the base tiles the move-scatter queues the plate hits
     of each wavefront and re-emits them together (in FP64 the queue overflows
     and the rest run in place); with 4x tiles it takes the two-pass path whose
-    move is the single-loop flight.  All must give the same states."""
-    p = Params(kn=0.4, body_force=0.02, n_cells=120, particles_per_cell=70, dt=3.0, seed=91,
+    move is the single-loop flight.  All must give the same states.  (The
+    instance has more than 16384 particles, so its base tiles are the full
+    register tiles.)"""
+    p = Params(kn=0.4, body_force=0.02, n_cells=240, particles_per_cell=70, dt=3.0, seed=91,
                n_transient=0, precision=getattr(D, prec_name))
     out = []
     for tm in (1, 4):
