@@ -38,6 +38,11 @@ CASES = [
     ("open_patch_kn0.2", dict(kn=0.2, body_force=synth.training_force(0.2), n_cells=85,
                               particles_per_cell=50, domain_length=0.425), dict(u=0.05, dudy=0.015)),
     ("closed_kn0.2_60x48", dict(kn=0.2, body_force=0.01, n_cells=60, particles_per_cell=48), None),
+    # at the limits: 256 keys and 6144 slots; 255 cells and the key of the
+    # particles that left
+    ("closed_limits_256x24", dict(kn=0.3, body_force=0.01, n_cells=256, particles_per_cell=24), None),
+    ("open_limits_255x16", dict(kn=0.2, body_force=0.01, n_cells=255, particles_per_cell=16,
+                                domain_length=0.5), dict(u=0.02, dudy=0.05)),
 ]
 
 
@@ -179,3 +184,19 @@ def test_two_resident_lanes_equal_alone(D):
             s.sync()
             for a, b in zip(s.get_state(), st2):
                 assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+@pytest.mark.parametrize("kw", [dict(n_cells=257, particles_per_cell=20),       # 257 keys
+                                dict(n_cells=256, particles_per_cell=25),       # 6400 slots
+                                dict(n_cells=256, particles_per_cell=16, domain_length=0.5)],  # 257 keys open
+                         ids=["keys", "slots", "open_keys"])
+def test_just_past_the_limits_is_multi_kernel(D, kw):
+    """One key or one tile of slots past the limits the lane is stepped by
+    the multi-kernel path, and the results are those of an explicit
+    multi-kernel group."""
+    p = Params(kn=0.3, body_force=0.01, seed=23, n_transient=5, precision=D.DSMC_FP32_FAST, **kw)
+    inflow = dict(u=0.02, dudy=0.05) if kw.get("domain_length") else None
+    res, prof = _run(D, [p], inflow, True, (19,))
+    ref, _ = _run(D, [p], inflow, False, (19,))
+    assert prof["count"] > 0 and prof["move_scatter"] > 0
+    _assert_same(res[0], ref[0])
