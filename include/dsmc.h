@@ -285,10 +285,9 @@ int dsmc_group_destroy(dsmc_group *g);
  * FP64): the global sort orders particles by bucket and the collide
  * workgroup of the bucket sorts it by cell in LDS.  For fuller cells it packs
  * cells into one LDS-staged collide workgroup (default one cell each).
- * 0 keeps the automatic choice.  The particle states do not depend on
- * either.  The window sums of small-cell instances may differ in their last
- * bits, because the lanes per cell that add a cell's moments up follow the
- * bucket size. */
+ * 0 keeps the automatic choice.  Results (particle states and window sums)
+ * do not depend on either: the lanes per cell that add up a cell's moments
+ * are the instance's own, whatever the bucket size. */
 int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t particles_per_block);
 /* Resident stepping of small instances (on by default).  When every member
  * of a lane is small -- a fast mode, fewer than 256 particles per collision

@@ -470,7 +470,10 @@ int build_lane(dsmc_group* g, Lane& lane) {
                               d.phase_mask == (uint32_t)DSMC_PHASE_ALL;
         int64_t base_items = h->plan.tile_items;
         if (bucketed) {
-            const int target = g->ppb > 0 ? g->ppb : (g->mode == kFp32Fast ? 2048 : 1024);
+            // buckets of about `target` particles; a lane starved of
+            // workgroups takes a quarter of the usual size
+            const int usual = g->mode == kFp32Fast ? 2048 : 1024;
+            const int target = g->ppb > 0 ? g->ppb : (fine_tiles ? usual / 4 : usual);
             d.key_shift = bucket_shift(per_cell, target);
             d.nkeys = ((d.Cc + (1 << d.key_shift) - 1) >> d.key_shift) + d.open;
             d.kcount = h->bucket_count;
@@ -501,10 +504,14 @@ int build_lane(dsmc_group* g, Lane& lane) {
             // one lane per cell, 64 cells per wavefront
             for (int c = 0; c < d.Cc; c += 64) gblocks.push_back(make_int4(i, c, std::min(c + 64, d.Cc), 64));
         } else if (bucketed) {
-            // one workgroup per bucket; groups of G lanes per cell, with G
-            // raised so that a bucket's cells occupy the workgroup's lanes
+            // one workgroup per bucket; groups of G lanes per cell.  G is the
+            // instance's own (the lanes per cell that fill a workgroup with a
+            // bucket of the usual size), never the launch shape's: the lanes
+            // that add up a cell's moments set the rounding of its sums, which
+            // therefore do not depend on the bucket size, the tuning or the lane
             const int cpk = 1 << d.key_shift;
-            const int G = std::min(64, std::max(group_width(per_cell), kFastWaves * 64 / cpk));
+            const int cpk_usual = 1 << bucket_shift(per_cell, g->mode == kFp32Fast ? 2048 : 1024);
+            const int G = std::min(64, std::max(group_width(per_cell), kFastWaves * 64 / cpk_usual));
             for (int b = 0; b < d.nkeys - d.open; ++b) gblocks.push_back(make_int4(i, b, G, 0));
             const double per_block = per_cell * cpk;
             group_cap = std::max(group_cap, (int)std::ceil(per_block + 4.0 * std::sqrt(per_block) + 32.0));

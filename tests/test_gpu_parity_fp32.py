@@ -246,14 +246,17 @@ def test_launch_shape_does_not_change_results(D):
         g.set_tuning(tile_mult, ppb)
         g.step(17)
         g.sync()
-        results.append([s.get_state() for s in sols])
+        results.append([(s.get_state(), s.sample(raw=True)["raw"]) for s in sols])
         g.close()
         for s in sols:
             s.close()
+    # states and window sums alike: the lanes per cell that add a cell's
+    # moments are the instance's own, not the launch shape's
     for other in results[1:]:
-        for sa, sb in zip(results[0], other):
+        for (sa, ra), (sb, rb) in zip(results[0], other):
             for a, b in zip(sa, sb):
                 assert np.array_equal(np.asarray(a), np.asarray(b))
+            assert np.array_equal(ra, rb)
 
 
 def test_group_membership_changes(D):

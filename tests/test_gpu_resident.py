@@ -149,9 +149,8 @@ def test_set_resident_argument_check(D):
 def test_two_resident_lanes_equal_alone(D):
     """520 small instances (2.08e6 particles) run in two lanes, each of them
     resident; members equal themselves stepped alone, also after the group is
-    autotuned (the autotune's steps use other bucket sizes, so other lanes
-    per cell: the states stay the same, the window sums may differ in the
-    last bits, and only the states are compared after it)."""
+    autotuned (the autotune's steps use other tiles and bucket sizes, which
+    change neither the states nor the window sums)."""
     ps = [Params(kn=0.5 + 0.01 * (r % 7), body_force=0.01, n_cells=80, particles_per_cell=50,
                  seed=synth.seed_of(15, r), n_transient=5, precision=D.DSMC_FP32_FAST)
           for r in range(520)]
@@ -169,11 +168,11 @@ def test_two_resident_lanes_equal_alone(D):
     before = [(sols[i].get_state(), sols[i].sample(raw=True)["raw"]) for i in picks]
     g.autotune()
     g.sync()
-    after = [sols[i].get_state() for i in picks]
+    after = [(sols[i].get_state(), sols[i].sample(raw=True)["raw"]) for i in picks]
     g.close()
     for s in sols:
         s.close()
-    for i, (st, raw), st2 in zip(picks, before, after):
+    for i, (st, raw), (st2, raw2) in zip(picks, before, after):
         with D.Solver(ps[i]) as s:
             s.step(24)
             s.sync()
@@ -184,6 +183,7 @@ def test_two_resident_lanes_equal_alone(D):
             s.sync()
             for a, b in zip(s.get_state(), st2):
                 assert np.array_equal(np.asarray(a), np.asarray(b))
+            assert np.array_equal(s.sample(raw=True)["raw"], raw2)
 
 
 @pytest.mark.parametrize("kw", [dict(n_cells=257, particles_per_cell=20),       # 257 keys
