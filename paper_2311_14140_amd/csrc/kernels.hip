@@ -2221,11 +2221,11 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
             hipLaunchKernelGGL((k_count<R, false>), dim3(w.n_tiles), dim3(kParticleThreads), hist_lds,
                                st, w.desc, w.tiles);
         mark(1);
-        if (w.count_scan_lds) {
+        if (w.scan_small_lds) {
             // the three column scans in one launch, in the scan slot
             mark(2);
             hipLaunchKernelGGL(k_scan_small, dim3(w.n_inst), dim3(kScanThreads),
-                               (size_t)w.count_scan_lds, st, w.desc);
+                               (size_t)w.scan_small_lds, st, w.desc);
             mark(3);
         } else {
             hipLaunchKernelGGL(k_colsum, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);

@@ -33,7 +33,7 @@ struct Work {
     int resident_cap;       // particle slots each resident workgroup holds in LDS
     // > 0: every instance's count matrix fits one workgroup's LDS, and k_scan_small
     // (this many bytes of it) replaces the three column-scan kernels
-    int count_scan_lds;
+    int scan_small_lds;
 };
 
 void launch_init(const InstDesc& d, const InstDesc* d_desc, Mode mode, hipStream_t s);

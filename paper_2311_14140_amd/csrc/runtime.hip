@@ -395,6 +395,9 @@ int group_width(double per_cell) {
     return G;
 }
 
+// Particles per sort bucket of a small-cell instance, unless tuned.
+int usual_bucket(int mode) { return mode == kFp32Fast ? 2048 : 1024; }
+
 // log2 of the cells per sort bucket of a small-cell instance: the largest
 // power of two of cells holding at most about `target` particles.
 int bucket_shift(double per_cell, int target) {
@@ -472,7 +475,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
         if (bucketed) {
             // buckets of about `target` particles; a lane starved of
             // workgroups takes a quarter of the usual size
-            const int usual = g->mode == kFp32Fast ? 2048 : 1024;
+            const int usual = usual_bucket(g->mode);
             const int target = g->ppb > 0 ? g->ppb : (fine_tiles ? usual / 4 : usual);
             d.key_shift = bucket_shift(per_cell, target);
             d.nkeys = ((d.Cc + (1 << d.key_shift) - 1) >> d.key_shift) + d.open;
@@ -510,7 +513,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
             // that add up a cell's moments set the rounding of its sums, which
             // therefore do not depend on the bucket size, the tuning or the lane
             const int cpk = 1 << d.key_shift;
-            const int cpk_usual = 1 << bucket_shift(per_cell, g->mode == kFp32Fast ? 2048 : 1024);
+            const int cpk_usual = 1 << bucket_shift(per_cell, usual_bucket(g->mode));
             const int G = std::min(64, std::max(group_width(per_cell), kFastWaves * 64 / cpk_usual));
             for (int b = 0; b < d.nkeys - d.open; ++b) gblocks.push_back(make_int4(i, b, G, 0));
             const double per_block = per_cell * cpk;
@@ -554,15 +557,15 @@ int build_lane(dsmc_group* g, Lane& lane) {
     if (!all_small || resident_lds_bytes((Mode)g->mode, resident_cap) > (size_t)resident_max_lds())
         resident.clear();
     // the column scans in one workgroup per instance when every count matrix is small
-    int count_scan_entries = 0;
+    int scan_small_entries = 0;
     bool small_counts = resident.empty() && n > 0 &&
                         (g->phase & (DSMC_PHASE_MOVE | DSMC_PHASE_SORT)) == (DSMC_PHASE_MOVE | DSMC_PHASE_SORT);
     for (const InstDesc& d : descs) {
         const int64_t e = (int64_t)d.tiles * d.nkeys;
         small_counts &= d.nkeys <= kScanThreads && e <= kCountScanEntries;
-        count_scan_entries = std::max<int>(count_scan_entries, (int)std::min<int64_t>(e, INT32_MAX));
+        scan_small_entries = std::max<int>(scan_small_entries, (int)std::min<int64_t>(e, INT32_MAX));
     }
-    const int count_scan_lds = small_counts ? std::max(count_scan_entries, 1) * (int)sizeof(int) : 0;
+    const int scan_small_lds = small_counts ? std::max(scan_small_entries, 1) * (int)sizeof(int) : 0;
 
     auto bytes_of = [](size_t k, size_t sz) { return align_up(sz * std::max<size_t>(k, 1)); };
     const size_t need = bytes_of(n, sizeof(InstDesc)) + bytes_of(tiles.size(), sizeof(int2)) +
@@ -613,7 +616,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
     w.resident = d_res;
     w.n_resident = (int)resident.size();
     w.resident_cap = resident_cap;
-    w.count_scan_lds = count_scan_lds;
+    w.scan_small_lds = scan_small_lds;
     return DSMC_OK;
 }
 
@@ -1232,7 +1235,7 @@ int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
             // and prefixes
             const Work& w = g->lanes[b % nl].work;
             for (int i = 0; i < 6; ++i) {
-                if ((w.n_resident && i < 5) || (w.count_scan_lds && (i == 1 || i == 3))) continue;
+                if ((w.n_resident && i < 5) || (w.scan_small_lds && (i == 1 || i == 3))) continue;
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, ev[7 * b + i], ev[7 * b + i + 1]) == hipSuccess) acc[i] += ms;
             }
