@@ -212,8 +212,9 @@ int device_max_lds() {
     std::lock_guard<std::mutex> lk(mu);
     if (cached < 0) {
         // Largest dynamic LDS a workgroup may use: the device's per-block limit
-        // if the kernels accept it, else 64 KiB.  Errors of the probing calls
-        // are cleared so they do not surface at a later launch.
+        // less room for the kernels' static shared variables, if the kernels
+        // accept it, else 64 KiB.  Errors of the probing calls are cleared so
+        // they do not surface at a later launch.
         int dev = 0, v = 65536;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
@@ -221,9 +222,9 @@ int device_max_lds() {
         (void)hipGetLastError();
         cached = 65536;
         hipError_t e1 = hipSuccess, e2 = hipSuccess;
-        if (v > 65536) {
-            e1 = dsmc::configure_kernels((size_t)v);
-            if (e1 == hipSuccess) cached = v;
+        if (v - 1024 > 65536) {
+            e1 = dsmc::configure_kernels((size_t)(v - 1024));
+            if (e1 == hipSuccess) cached = v - 1024;
             (void)hipGetLastError();
         }
         if (cached == 65536) {
