@@ -514,7 +514,10 @@ int build_lane(dsmc_group* g, Lane& lane) {
             // that add up a cell's moments set the rounding of its sums, which
             // therefore do not depend on the bucket size, the tuning or the lane
             const int cpk = 1 << d.key_shift;
-            const int cpk_usual = 1 << bucket_shift(per_cell, usual_bucket(g->mode));
+            // (an instance with fewer cells than a usual bucket fills the
+            // workgroup with its cells alone)
+            int cpk_usual = 1 << bucket_shift(per_cell, usual_bucket(g->mode));
+            while (cpk_usual > 1 && cpk_usual / 2 >= d.Cc) cpk_usual /= 2;
             const int G = std::min(64, std::max(group_width(per_cell), kFastWaves * 64 / cpk_usual));
             for (int b = 0; b < d.nkeys - d.open; ++b) gblocks.push_back(make_int4(i, b, G, 0));
             const double per_block = per_cell * cpk;
