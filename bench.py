@@ -62,13 +62,17 @@ def kernel_bytes(phase: str, N: int, Cc: int, rb: int, coll_frac: float, samplin
 
 
 PROFILE_TAGS = {"cfg1": "kernels_cfg1_kn0.1_300x1000_fp32",
+                "cfg2": "kernels_cfg2_kn0.01_1000x20000_fp32",
                 "cfg3": "kernels_cfg3_batched256_fp32"}
+# sources whose change invalidates the committed counters: the kernels and the
+# runtime that chooses their launch shapes
+TRAFFIC_SOURCES = ("kernels.hip", "runtime.hip", "rng.hpp", "common.hpp", "kernels.hpp")
 
 
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "rng.hpp", "common.hpp"):
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_2311_14140_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -165,6 +169,36 @@ def fp64_plain(dsmc, torch, params_list, steps):
             "note": "each instance alone, sequential-per-cell NTC, bit-identical to the oracle"}
 
 
+def fp64_fast_rates(dsmc, torch, plist, sample, steps):
+    """The parallel-NTC scheme of the fast mode with FP64 state: the sampled
+    instances each alone, and the whole workload as one group."""
+    FP64_FAST = dsmc.DSMC_FP64_FAST
+    ps_total, el_total = 0, 0.0
+    for p in sample:
+        with dsmc.Solver(p.with_(n_transient=0, precision=FP64_FAST)) as d:
+            d.step(10)
+            el_total += _timed(torch, d.step, d.sync, steps)
+            ps_total += d.N * steps
+    alone = {"value": ps_total / el_total, "unit": "particle-steps/s", "steps": steps,
+             "instances": len(sample)}
+    sols = [dsmc.Solver(p.with_(n_transient=0, precision=FP64_FAST)) for p in plist]
+    g = dsmc.Group()
+    try:
+        for s in sols:
+            g.add(s)
+        g.step(16)
+        el = _timed(torch, g.step, g.sync, steps)
+        N = sum(s.N for s in sols)
+    finally:
+        g.close()
+        for s in sols:
+            s.close()
+    batched = {"value": N * steps / el, "unit": "particle-steps/s", "steps": steps,
+               "instances": len(plist), "ms_per_step": 1e3 * el / steps}
+    return {"alone": alone, "batched": batched, "dtype": "f64",
+            "note": "the fast mode's parallel NTC with FP64 positions and velocities"}
+
+
 def serve(n_requests, rate_hz, precision, batched, budget):
     """Serve the first n requests of the Poisson trace; returns the summary."""
     import synth
@@ -204,12 +238,69 @@ def cpu_oracle_rate(params_list, seconds: float):
     return ps / el, ps, el
 
 
+def host_cores() -> int:
+    """Cores this process may use, capped at 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def host_identity() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cores": host_cores(), "cpu_model": model}
+
+
+def cpu_oracle_rate_all_cores(params_list, seconds: float, threads: int):
+    """Aggregate oracle throughput on ``threads`` host cores: every thread
+    steps its own independent instances (the oracle's C calls release the
+    interpreter lock) for about ``seconds`` of wall time."""
+    import threading
+    import oracle
+    from synth import FP64_DETERMINISTIC
+    work = [[] for _ in range(threads)]
+    for i, p in enumerate(params_list):
+        work[i % threads].append(p)
+    work = [w for w in work if w]
+    orcs = [[oracle.Oracle(p.with_(precision=FP64_DETERMINISTIC)) for p in w] for w in work]
+    done = [0] * len(orcs)
+    t0 = time.perf_counter()
+    stop = t0 + seconds
+
+    def run(k):
+        while time.perf_counter() < stop:
+            for o in orcs[k]:
+                o.step(2)
+                done[k] += 2 * o.N
+                if time.perf_counter() >= stop:
+                    break
+
+    ts = [threading.Thread(target=run, args=(k,)) for k in range(len(orcs))]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    el = time.perf_counter() - t0
+    return sum(done) / el, sum(done), el, len(ts)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="cfg3", choices=["cfg0", "cfg1", "cfg2", "cfg3"])
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the automatic launch shape of the batched mix")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--fp64-steps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -217,8 +308,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the single-instance workloads and the served stream")
     ap.add_argument("--extra-steps", type=int, default=200)
-    ap.add_argument("--serve-requests", type=int, default=40,
-                    help="requests of the Poisson trace to serve in each mode (2000 = full)")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the Poisson trace served FP32-batched (2000 = the full trace)")
+    ap.add_argument("--serve-plain-requests", type=int, default=40,
+                    help="requests of the same trace served by the plain FP64 path")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of the plain device copy run after the timed region, whose "
                          "HBM counters calibrate the kernels' (0 = skip)")
@@ -239,8 +332,9 @@ def main():
         print("# " + msg, file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
+    tune_budget = 0 if (args.workload != "cfg3" or args.no_autotune) else 64
     if args.workload == "cfg3":
-        plist = [p.with_(n_transient=args.warmup) for p in synth.config3_instances(256)]
+        plist = [p.with_(n_transient=args.warmup + tune_budget) for p in synth.config3_instances(256)]
         wdesc = f"cfg3: {MIX_DESC}, FP32 velocities + FP64 accumulators, one group"
     else:
         base, _ = WORKLOADS[args.workload]
@@ -252,7 +346,28 @@ def main():
     N, Cc = sub.N, sub.Cc
     log(f"workload {args.workload}: {len(plist)} instance(s), N={N}, collision cells={Cc}, "
         f"warmup={args.warmup} steps={args.steps}")
-    sub.step(args.warmup)
+    tuning = None
+    if tune_budget:
+        t = time.perf_counter()
+        tm, ppb, wpc = sub.group.autotune()
+        # the tuner's steps are transient steps of the members: the warm-up
+        # makes up the rest, so the timed steps are sampling steps
+        small = min(range(len(sub.sols)), key=lambda i: sub.sols[i].N)
+        done = sub.sols[small].get_state()[5]
+        tuning = {"tile_mult": tm, "particles_per_block": ppb, "waves_per_cu": wpc,
+                  "tuner_steps": done, "tuner_seconds": time.perf_counter() - t,
+                  "searched": "tile_mult {1,2,4} x particles_per_block {auto,1024,4096} "
+                              "at automatic occupancy, then waves_per_cu {8,12,16}"}
+        log(f"autotuned: tile_mult={tm} particles_per_block={ppb} waves_per_cu={wpc} "
+            f"({done} steps)")
+        sub.step(max(0, args.warmup + tune_budget - done))
+    else:
+        sub.step(args.warmup)
+    sub.sync()
+    sub.sample()
+    # one more graph chunk past the warm-up: the step graphs are captured when
+    # a group's lanes are built, and this replays them once before timing
+    sub.step(8)
     sub.sync()
     sub.sample()
 
@@ -285,14 +400,19 @@ def main():
     log("per-kernel ms/step: " + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()))
     sub.close()
 
-    # ---- the plain FP64 path on the same instances (a sample of the mix)
-    fp64 = None
+    # ---- the FP64 paths on the same instances (a sample of the mix): the
+    # plain deterministic path (sequential per-cell NTC), and the parallel NTC
+    # of the fast mode in FP64, alone and as one group
+    fp64 = fp64_fast = None
     if args.fp64_steps > 0:
         sample = plist[::16]
         fp64 = fp64_plain(dsmc, torch, sample, args.fp64_steps)
         fp64["sample"] = f"{len(sample)} instances (every 16th), {args.fp64_steps} steps each" \
             if len(plist) > 1 else "the same instance"
         log(f"fp64 plain: {fp64['value']:.4e} particle-steps/s")
+        fp64_fast = fp64_fast_rates(dsmc, torch, plist, sample, args.fp64_steps)
+        log(f"fp64 fast: alone {fp64_fast['alone']['value']:.4e}, "
+            f"batched {fp64_fast['batched']['value']:.4e} particle-steps/s")
 
     # ---- other workloads of the same hot path, and the served stream
     extra, serving = {}, None
@@ -300,7 +420,7 @@ def main():
         extra["cfg1_single_instance"] = time_single(dsmc, torch, WORKLOADS["cfg1"][0],
                                                     args.extra_steps, "cfg1")
         log(f"cfg1: {extra['cfg1_single_instance']['value']:.4e}")
-        extra["cfg2_large_instance"] = time_single(dsmc, torch, WORKLOADS["cfg2"][0].with_(n_sub=2),
+        extra["cfg2_large_instance"] = time_single(dsmc, torch, WORKLOADS["cfg2"][0],
                                                    max(2, args.extra_steps // 10), "cfg2")
         log(f"cfg2: {extra['cfg2_large_instance']['value']:.4e}")
         from paper_2311_14140_amd.hybrid import time_patch_group
@@ -317,17 +437,27 @@ def main():
             free, _ = torch.cuda.mem_get_info()
             budget = int(0.8 * free)
             fp32 = serve(args.serve_requests, 200.0, synth.FP32_FAST, True, budget)
-            log(f"served FP32 batched: p50 {fp32['p50_s']:.3f} s, p99 {fp32['p99_s']:.3f} s")
-            plain = serve(args.serve_requests, 200.0, synth.FP64_DETERMINISTIC, False, budget)
-            log(f"served FP64 plain: p50 {plain['p50_s']:.3f} s, p99 {plain['p99_s']:.3f} s")
+            log(f"served FP32 batched ({args.serve_requests} requests at 200/s): "
+                f"p50 {fp32['p50_s']:.3f} s, p99 {fp32['p99_s']:.3f} s")
+            plain = None
+            if args.serve_plain_requests > 0:
+                plain = serve(args.serve_plain_requests, 200.0, synth.FP64_DETERMINISTIC, False,
+                              budget)
+                log(f"served FP64 plain ({args.serve_plain_requests} requests): "
+                    f"p50 {plain['p50_s']:.3f} s, p99 {plain['p99_s']:.3f} s")
+            # capacity: requests/s the batched path sustains, from the
+            # saturated run's throughput and the mean work of a request
             per_req = fp32["particle_steps"] / max(1, fp32["served"])
-            cap = rate / per_req   # requests/s the batched path sustains
+            cap = fp32["throughput"] / per_req
             low = serve(args.serve_requests, 0.7 * cap, synth.FP32_FAST, True, budget)
-            log(f"served FP32 at 0.7 capacity ({0.7 * cap:.1f}/s): p50 {low['p50_s']:.3f} s")
-            serving = {"trace": f"first {args.serve_requests} requests of the Poisson trace "
-                                f"(mean 200/s, parameters from the batched-mix distribution, "
-                                f"transient per Kn + 5000 sampling steps each)",
-                       "budget_bytes": budget, "fp32_batched": fp32, "fp64_plain": plain,
+            log(f"served FP32 at 0.7 capacity ({0.7 * cap:.1f}/s): p50 {low['p50_s']:.3f} s, "
+                f"p99 {low['p99_s']:.3f} s")
+            serving = {"trace": f"Poisson trace (PCG64 seeds 4 and 40), parameters from the "
+                                f"batched-mix distribution, transient per Kn + 5000 sampling "
+                                f"steps each; FP32 batched: the first {args.serve_requests} "
+                                f"requests; FP64 plain: the first {args.serve_plain_requests}",
+                       "budget_bytes": budget, "capacity_req_per_s": cap,
+                       "fp32_batched": fp32, "fp64_plain": plain,
                        "fp32_batched_0.7_capacity": low}
 
     # a plain copy of known size (outside the timed region): what the
@@ -344,13 +474,22 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         sample = plist[::16]
-        r, ps, sec = cpu_oracle_rate(sample, args.cpu_seconds)
-        cpu = {"value": r, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"{ps} particle-steps: {len(sample)} instance(s) of the workload "
-                         f"stepped in turn from their initial state, FP64, one thread, "
-                         f"{sec:.1f} s of stepping"}
-        log(f"cpu oracle: {r:.4e} particle-steps/s")
+        host = host_identity()
+        r1, ps1, sec1 = cpu_oracle_rate(sample, args.cpu_seconds)
+        log(f"cpu oracle, one core: {r1:.4e} particle-steps/s")
+        # every core: the whole mix, instances dealt to the threads
+        rn, psn, secn, used = cpu_oracle_rate_all_cores(plist, args.cpu_seconds, host["usable_cores"])
+        log(f"cpu oracle, {used} cores: {rn:.4e} particle-steps/s")
+        cpu = {"value": rn, "unit": "particle-steps/s", "cores": used, "kind": "oracle",
+               "sample": f"{psn} particle-steps in {secn:.1f} s: the {len(plist)} instance(s) of "
+                         f"the workload dealt to {used} threads, each stepping its own from "
+                         f"their initial state, FP64",
+               "one_core": {"value": r1, "cores": 1,
+                            "sample": f"{ps1} particle-steps: {len(sample)} instance(s) (every "
+                                      f"16th) stepped in turn, one thread, {sec1:.1f} s"},
+               "host": host}
 
+    survey_bytes = 79.0 * N if rb == 4 else 149.0 * N
     line = {
         "metric": METRIC,
         "value": rate,
@@ -372,10 +511,15 @@ def main():
                      "algorithmic_bytes_per_launch": dom_bytes, "launches_per_step": lanes},
         "step_roofline": {"algorithmic_bytes_per_step": step_bytes,
                           "achieved_GBps": step_bytes / (el / args.steps) / 1e9,
-                          "frac": step_bytes / (el / args.steps) / 1e9 / HBM_PEAK_GBS},
+                          "frac": step_bytes / (el / args.steps) / 1e9 / HBM_PEAK_GBS,
+                          "three_pass_bytes_per_step": survey_bytes,
+                          "three_pass_frac": survey_bytes / (el / args.steps) / 1e9 / HBM_PEAK_GBS},
         "kernel_ms_per_step": kern,
+        "tuning": tuning,
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": rate / fp64["value"] if fp64 else None,
+        "fp64_fast": fp64_fast,
+        "speedup_vs_fp64_fast_batched": rate / fp64_fast["batched"]["value"] if fp64_fast else None,
         "serving": serving,
         "cpu_baseline": cpu,
         "other_workloads": extra,

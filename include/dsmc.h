@@ -285,10 +285,16 @@ int dsmc_group_destroy(dsmc_group *g);
  * FP64): the global sort orders particles by bucket and the collide
  * workgroup of the bucket sorts it by cell in LDS.  For fuller cells it packs
  * cells into one LDS-staged collide workgroup (default one cell each).
- * 0 keeps the automatic choice.  Results (particle states and window sums)
- * do not depend on either: the lanes per cell that add up a cell's moments
- * are the instance's own, whatever the bucket size. */
-int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t particles_per_block);
+ * waves_per_cu (0, or 4..32) caps the wavefronts of the count, move-scatter
+ * and collide kernels that share a CU: each 4-wavefront workgroup then asks
+ * for 1/(waves_per_cu/4) of the CU's LDS, so at most that many fit.  0 keeps
+ * the automatic choice (for waves_per_cu: what registers and the LDS the
+ * kernels use allow).  Results (particle states and window sums) do not
+ * depend on any of them: the lanes per cell that add up a cell's moments
+ * are the instance's own, whatever the bucket size.  INVALID_ARG out of
+ * range. */
+int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t particles_per_block,
+                          int32_t waves_per_cu);
 /* Resident stepping of small instances (on by default).  When every member
  * of a lane is small -- a fast mode, fewer than 256 particles per collision
  * cell, at most 256 collision cells (255 for an open instance) and at most
@@ -302,14 +308,17 @@ int dsmc_group_set_tuning(dsmc_group *g, int32_t tile_mult, int32_t particles_pe
  * collide slot, and its other slots read 0.  INVALID_ARG unless enable is 0
  * or 1. */
 int dsmc_group_set_resident(dsmc_group *g, int32_t enable);
-/* Time every pair of tile_mult in {1, 2, 4} and particles_per_block in
- * {0, 1024, 4096} on the group's own steps (4 steps each; they are real
- * steps of the members) and keep the fastest.  The choice is cached per group
- * shape (precision and the particles and collision cells of every member), in
- * the process and, if DSMC_AUTOTUNE_CACHE names a file, across processes.
- * Writes the choice to *tile_mult / *particles_per_block (either may be NULL).
- * STATE if the group is empty. */
-int dsmc_group_autotune(dsmc_group *g, int32_t *tile_mult, int32_t *particles_per_block);
+/* Choose the group's launch shape on its own steps: every pair of tile_mult
+ * in {1, 2, 4} and particles_per_block in {0, 1024, 4096} at the automatic
+ * occupancy, then waves_per_cu in {8, 12, 16} at the fastest pair (4 steps
+ * per shape, 3 of them timed with HIP events on the group's stream; they
+ * are real steps of the members), keeping the fastest of all.  The choice is
+ * cached per group shape (precision and the particles and collision cells of
+ * every member), in the process and, if DSMC_AUTOTUNE_CACHE names a file,
+ * across processes.  Writes the choice to the three out-parameters (any may
+ * be NULL).  STATE if the group is empty. */
+int dsmc_group_autotune(dsmc_group *g, int32_t *tile_mult, int32_t *particles_per_block,
+                        int32_t *waves_per_cu);
 
 #ifdef __cplusplus
 }

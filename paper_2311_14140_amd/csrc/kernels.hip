@@ -2200,7 +2200,10 @@ void resident_kernel(const Work& w, Mode mode, int64_t n_steps, hipStream_t st) 
 
 template <class R>
 void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipEvent_t* ev = nullptr) {
-    const size_t hist_lds = (size_t)w.max_cc * sizeof(int);
+    // a tuning may raise the dynamic LDS of the particle and collide kernels
+    // above what they use, to cap the workgroups that share a CU
+    auto lds = [&](size_t need) { return need > w.lds_floor ? need : w.lds_floor; };
+    const size_t hist_lds = lds((size_t)w.max_cc * sizeof(int));
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
@@ -2237,11 +2240,11 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
         mark(4);
         if (w.has_open)
             hipLaunchKernelGGL((k_move_scatter<R, true>), dim3(w.n_tiles), dim3(kParticleThreads),
-                               scatter_lds_bytes(mode, w.max_cc, w.stage_max), st, w.desc, w.tiles,
+                               lds(scatter_lds_bytes(mode, w.max_cc, w.stage_max)), st, w.desc, w.tiles,
                                w.stage_max);
         else
             hipLaunchKernelGGL((k_move_scatter<R, false>), dim3(w.n_tiles), dim3(kParticleThreads),
-                               scatter_lds_bytes(mode, w.max_cc, w.stage_max), st, w.desc, w.tiles,
+                               lds(scatter_lds_bytes(mode, w.max_cc, w.stage_max)), st, w.desc, w.tiles,
                                w.stage_max);
     } else {
         step_kernels_debug<R>(w, mode, phase, st, mark);
@@ -2255,11 +2258,11 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
         } else {
             if (w.n_cblocks)
                 hipLaunchKernelGGL((k_collide_fast<R>), dim3(w.n_cblocks), dim3(64 * kFastWaves),
-                                   fast_collide_lds_bytes(mode, w.fast_cap), st, w.desc, w.cblocks,
+                                   lds(fast_collide_lds_bytes(mode, w.fast_cap)), st, w.desc, w.cblocks,
                                    w.fast_cap, do_collide);
             if (w.n_gblocks)
                 hipLaunchKernelGGL((k_collide_bucket<R>), dim3(w.n_gblocks), dim3(64 * kFastWaves),
-                                   bucket_collide_lds_bytes(mode, w.group_cap), st, w.desc,
+                                   lds(bucket_collide_lds_bytes(mode, w.group_cap)), st, w.desc,
                                    w.gblocks, w.group_cap, do_collide);
         }
     }

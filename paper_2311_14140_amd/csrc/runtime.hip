@@ -262,6 +262,23 @@ int resident_max_lds() {
     return cached;
 }
 
+// LDS of one CU (160 KiB on MI355X), shared by the workgroups resident on it.
+int cu_lds_bytes() {
+    static int cached = -1;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cached < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+            v <= 0)
+            v = 160 * 1024;
+        (void)hipGetLastError();
+        cached = v;
+    }
+    return cached;
+}
+
 }  // namespace
 
 struct dsmc_group;
@@ -328,6 +345,7 @@ struct dsmc_group {
     bool dirty = true;
     int tile_mult = 0;   // 0 = automatic
     int ppb = 0;         // target particles per fast-collide workgroup, 0 = automatic
+    int waves_per_cu = 0;  // occupancy cap of the particle and collide kernels, 0 = automatic
     bool resident = true;  // lanes of small instances step them in one workgroup each
     unsigned phase = DSMC_PHASE_ALL;
     int n_lanes = 1;     // lanes in use (lanes.size() may be larger)
@@ -621,17 +639,51 @@ int build_lane(dsmc_group* g, Lane& lane) {
     w.n_resident = (int)resident.size();
     w.resident_cap = resident_cap;
     w.scan_small_lds = scan_small_lds;
+    // occupancy cap: the count, move-scatter and collide workgroups are 4
+    // wavefronts; asking each for 1/k of the CU's LDS (less a margin for
+    // static shared variables and allocation granularity) lets at most k
+    // share a CU
+    w.lds_floor = 0;
+    if (g->waves_per_cu > 0) {
+        const int per_cu = std::max(1, g->waves_per_cu / 4);
+        const int floor_bytes = cu_lds_bytes() / per_cu - 2048;
+        w.lds_floor = (size_t)std::max(0, std::min(floor_bytes, max_lds));
+    }
+    return DSMC_OK;
+}
+
+// Capture the lane's graph of kGraphSteps whole steps when the lane is
+// built.  Capture only records the launches (no kernel runs), so the first
+// steps that replay it pay no capture or instantiation.  Resident lanes and
+// debug phase masks launch directly and have no graph.
+int capture_lane(dsmc_group* g, Lane& l) {
+    if (l.members.empty() || l.work.n_resident || g->phase != DSMC_PHASE_ALL) return DSMC_OK;
+    if (!l.cap_stream) HIP_TRY(&g->err, hipStreamCreateWithFlags(&l.cap_stream, hipStreamNonBlocking));
+    HIP_TRY(&g->err, hipStreamBeginCapture(l.cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < kGraphSteps; ++k) launch_step(l.work, (Mode)g->mode, g->phase, l.cap_stream);
+    const hipError_t launched = hipGetLastError();
+    hipGraph_t graph = nullptr;
+    const hipError_t ended = hipStreamEndCapture(l.cap_stream, &graph);
+    if (launched != hipSuccess || ended != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(&g->err, DSMC_ERR_DEVICE,
+                    std::string("step graph capture: ") +
+                        hipGetErrorString(launched != hipSuccess ? launched : ended));
+    }
+    l.graph = graph;
+    HIP_TRY(&g->err, hipGraphInstantiate(&l.gexec, graph, nullptr, nullptr, 0));
     return DSMC_OK;
 }
 
 // (Re)build the lanes of a group: members are dealt to the lanes largest
 // first, each to the lane with the fewest particles so far.
 int rebuild(dsmc_group* g) {
-    drop_graphs(g);
-    // the streams may still be using the previous lists
+    // the streams may still be running the previous graphs and lists: wait
+    // for them before either is released
     HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
     for (Lane& l : g->lanes)
         if (l.stream) HIP_TRY(&g->err, hipStreamSynchronize(l.stream));
+    drop_graphs(g);
     int64_t total = 0;
     for (const dsmc_handle* h : g->members) total += h->plan.N;
     const int nl = (!g->solo && g->members.size() >= 2 && total >= kLaneMinParticles) ? kMaxLanes : 1;
@@ -659,7 +711,9 @@ int rebuild(dsmc_group* g) {
                    ? g->members[0]->p.debug_phase_mask
                    : (unsigned)DSMC_PHASE_ALL;
     for (int k = 0; k < nl; ++k) {
-        const int r = build_lane(g, g->lanes[k]);
+        int r = build_lane(g, g->lanes[k]);
+        if (r) return r;
+        r = capture_lane(g, g->lanes[k]);
         if (r) return r;
     }
     g->dirty = false;
@@ -683,26 +737,23 @@ int enqueue_steps(dsmc_group* g, int64_t n_steps) {
         int64_t left = n_steps;
         if (l.work.n_resident) {
             // whole steps in one launch per chunk
-            for (int64_t k = 0; k < n_steps; k += kResidentChunk)
+            for (int64_t k = 0; k < n_steps; k += kResidentChunk) {
                 launch_resident(l.work, mode, std::min<int64_t>(kResidentChunk, n_steps - k), st);
+                HIP_TRY(&g->err, hipGetLastError());
+            }
             left = 0;
         }
-        if (left >= kGraphSteps && g->phase == DSMC_PHASE_ALL) {
-            if (!l.gexec) {
-                if (!l.cap_stream) HIP_TRY(&g->err, hipStreamCreateWithFlags(&l.cap_stream, hipStreamNonBlocking));
-                HIP_TRY(&g->err, hipStreamBeginCapture(l.cap_stream, hipStreamCaptureModeThreadLocal));
-                for (int k = 0; k < kGraphSteps; ++k) launch_step(l.work, mode, g->phase, l.cap_stream);
-                hipGraph_t graph = nullptr;
-                HIP_TRY(&g->err, hipStreamEndCapture(l.cap_stream, &graph));
-                l.graph = graph;
-                HIP_TRY(&g->err, hipGraphInstantiate(&l.gexec, graph, nullptr, nullptr, 0));
-            }
+        // the graph was captured when the lane was built
+        if (l.gexec) {
             while (left >= kGraphSteps) {
                 HIP_TRY(&g->err, hipGraphLaunch(l.gexec, st));
                 left -= kGraphSteps;
             }
         }
-        for (int64_t k = 0; k < left; ++k) launch_step(l.work, mode, g->phase, st);
+        for (int64_t k = 0; k < left; ++k) {
+            launch_step(l.work, mode, g->phase, st);
+            HIP_TRY(&g->err, hipGetLastError());
+        }
         if (nl > 1) {
             HIP_TRY(&g->err, hipEventRecord(l.done, st));
             HIP_TRY(&g->err, hipStreamWaitEvent(g->stream, l.done, 0));
@@ -801,6 +852,40 @@ int prepare_group_sample(dsmc_group* g) {
     g->stage_doubles = tot;
     g->sample_version = g->version;
     return DSMC_OK;
+}
+
+// Member i's estimators from its block of a group sample's host staging
+// (at soff[i]: kEstPerCell * C estimator values, mass flow, sampled steps,
+// collisions, status) into outs[i].
+int unpack_group_sample(dsmc_group* g, dsmc_moments* outs, const double* stage, const int64_t* soff) {
+    const int n = (int)g->members.size();
+    int rc = DSMC_OK;
+    for (int i = 0; i < n; ++i) {
+        const int C = g->members[i]->plan.C;
+        const double* e = stage + soff[i];
+        dsmc_moments* out = &outs[i];
+        const int status = (int)e[(size_t)kEstPerCell * C + 3];
+        if (status) {
+            out->n_sampled_steps = -1;
+            if (rc == DSMC_OK) {
+                const char* why = (status & 1)   ? "non-finite particle velocity"
+                                  : (status & 2) ? "cell counts do not add up to N"
+                                  : (status & 4) ? "sorted slot out of range"
+                                                 : "open boundary: particle slots exhausted";
+                rc = fail(&g->err, DSMC_ERR_NUMERIC, "member " + std::to_string(i) + ": " + why);
+            }
+            continue;
+        }
+        double* dst[kEstPerCell] = {out->n,  out->ux, out->uy, out->uz,     out->T,
+                                    out->pxy, out->qx, out->qy, out->pxy_mid};
+        for (int m = 0; m < kEstPerCell; ++m)
+            if (dst[m]) std::memcpy(dst[m], e + (size_t)m * C, sizeof(double) * C);
+        const double K = e[(size_t)kEstPerCell * C + 1];
+        out->n_sampled_steps = (int64_t)K;
+        out->mass_flow = K > 0 ? e[(size_t)kEstPerCell * C] : NAN;
+        out->n_collisions = (int64_t)e[(size_t)kEstPerCell * C + 2];
+    }
+    return rc;
 }
 
 }  // namespace
@@ -1337,32 +1422,7 @@ int dsmc_group_sample(dsmc_group* g, dsmc_moments* outs, int32_t n_outs, int res
         HIP_TRY(&g->err, hipGetLastError());
     }
     HIP_TRY(&g->err, hipStreamSynchronize(s));
-    int rc = DSMC_OK;
-    for (int i = 0; i < n; ++i) {
-        const int C = g->members[i]->plan.C;
-        const double* e = g->h_stage + g->soff[i];
-        dsmc_moments* out = &outs[i];
-        const int status = (int)e[(size_t)kEstPerCell * C + 3];
-        if (status) {
-            out->n_sampled_steps = -1;
-            if (rc == DSMC_OK) {
-                const char* why = (status & 1)   ? "non-finite particle velocity"
-                                  : (status & 2) ? "cell counts do not add up to N"
-                                                 : "sorted slot out of range";
-                rc = fail(&g->err, DSMC_ERR_NUMERIC, "member " + std::to_string(i) + ": " + why);
-            }
-            continue;
-        }
-        double* dst[kEstPerCell] = {out->n,  out->ux, out->uy, out->uz,     out->T,
-                                    out->pxy, out->qx, out->qy, out->pxy_mid};
-        for (int m = 0; m < kEstPerCell; ++m)
-            if (dst[m]) std::memcpy(dst[m], e + (size_t)m * C, sizeof(double) * C);
-        const double K = e[(size_t)kEstPerCell * C + 1];
-        out->n_sampled_steps = (int64_t)K;
-        out->mass_flow = K > 0 ? e[(size_t)kEstPerCell * C] : NAN;
-        out->n_collisions = (int64_t)e[(size_t)kEstPerCell * C + 2];
-    }
-    return rc;
+    return unpack_group_sample(g, outs, g->h_stage, g->soff.data());
 }
 
 int dsmc_group_size(const dsmc_group* g, int32_t* n) {
@@ -1386,12 +1446,15 @@ int dsmc_group_destroy(dsmc_group* g) {
     return DSMC_OK;
 }
 
-int dsmc_group_set_tuning(dsmc_group* g, int32_t tile_mult, int32_t particles_per_block) {
+int dsmc_group_set_tuning(dsmc_group* g, int32_t tile_mult, int32_t particles_per_block,
+                          int32_t waves_per_cu) {
     if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
-    if (tile_mult < 0 || tile_mult > 16 || particles_per_block < 0 || particles_per_block > (1 << 20))
+    if (tile_mult < 0 || tile_mult > 16 || particles_per_block < 0 || particles_per_block > (1 << 20) ||
+        waves_per_cu < 0 || waves_per_cu > 32 || (waves_per_cu > 0 && waves_per_cu < 4))
         return fail(&g->err, DSMC_ERR_INVALID_ARG, "tuning out of range");
     g->tile_mult = tile_mult;
     g->ppb = particles_per_block;
+    g->waves_per_cu = waves_per_cu;
     g->dirty = true;
     return DSMC_OK;
 }
@@ -1408,8 +1471,12 @@ int dsmc_group_set_resident(dsmc_group* g, int32_t enable) {
 
 namespace {
 
+struct Tuning {
+    int tile_mult, ppb, waves_per_cu;
+};
+
 std::mutex g_tune_mu;
-std::vector<std::pair<std::string, std::pair<int, int>>> g_tune_cache;
+std::vector<std::pair<std::string, Tuning>> g_tune_cache;
 
 // Signature of a group's launch problem: precision and the (N, Cc) of every
 // member, so groups of the same shape reuse a tuning.
@@ -1426,12 +1493,11 @@ std::string group_signature(const dsmc_group* g) {
     return s + ":" + std::to_string(v.size()) + ":" + std::to_string(hsh);
 }
 
-bool tune_lookup(const std::string& sig, int* tm, int* ppb) {
+bool tune_lookup(const std::string& sig, Tuning* t) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto& e : g_tune_cache)
         if (e.first == sig) {
-            *tm = e.second.first;
-            *ppb = e.second.second;
+            *t = e.second;
             return true;
         }
     const char* path = std::getenv("DSMC_AUTOTUNE_CACHE");
@@ -1439,87 +1505,111 @@ bool tune_lookup(const std::string& sig, int* tm, int* ppb) {
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char key[256];
-    int a, b;
+    int a, b, c;
     bool found = false;
-    while (std::fscanf(f, "%255s %d %d", key, &a, &b) == 3)
+    while (std::fscanf(f, "%255s %d %d %d", key, &a, &b, &c) == 4)
         if (sig == key) {
-            *tm = a;
-            *ppb = b;
+            *t = Tuning{a, b, c};
             found = true;
         }
     std::fclose(f);
-    if (found) g_tune_cache.push_back({sig, {*tm, *ppb}});
+    if (found) g_tune_cache.push_back({sig, *t});
     return found;
 }
 
-void tune_store(const std::string& sig, int tm, int ppb) {
+void tune_store(const std::string& sig, const Tuning& t) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache.push_back({sig, {tm, ppb}});
+    g_tune_cache.push_back({sig, t});
     const char* path = std::getenv("DSMC_AUTOTUNE_CACHE");
     if (!path) return;
     if (FILE* f = std::fopen(path, "a")) {
-        std::fprintf(f, "%s %d %d\n", sig.c_str(), tm, ppb);
+        std::fprintf(f, "%s %d %d %d\n", sig.c_str(), t.tile_mult, t.ppb, t.waves_per_cu);
         std::fclose(f);
     }
+}
+
+// Device milliseconds of kTuneSteps steps of the group at one launch shape,
+// after one untimed step (which rebuilds the lanes and captures their graphs).
+constexpr int kTuneSteps = 3;
+int time_shape(dsmc_group* g, const Tuning& t, hipEvent_t e0, hipEvent_t e1, float* ms) {
+    g->tile_mult = t.tile_mult;
+    g->ppb = t.ppb;
+    g->waves_per_cu = t.waves_per_cu;
+    g->dirty = true;
+    int rc = enqueue_steps(g, 1);
+    if (rc) return rc;
+    HIP_TRY(&g->err, hipEventRecord(e0, g->stream));
+    rc = enqueue_steps(g, kTuneSteps);
+    if (rc) return rc;
+    HIP_TRY(&g->err, hipEventRecord(e1, g->stream));
+    HIP_TRY(&g->err, hipEventSynchronize(e1));
+    HIP_TRY(&g->err, hipEventElapsedTime(ms, e0, e1));
+    return DSMC_OK;
 }
 
 }  // namespace
 
 extern "C" {
 
-// Tries every (tile multiplier, particles per collide workgroup) pair on the
-// group's own steps (3 timed steps each after one untimed step, HIP events on
-// the group's stream) and keeps the fastest.  Results do not depend on the
-// launch shape, so these are ordinary steps of the members.
-int dsmc_group_autotune(dsmc_group* g, int32_t* tile_mult_out, int32_t* ppb_out) {
+// Coordinate search on the group's own steps: every pair of tile multiplier
+// and particles per collide workgroup (which sets the cells per block) at the
+// automatic occupancy, then the waves-per-CU caps at the best pair.  These
+// are ordinary steps of the members (results do not depend on the launch
+// shape).
+int dsmc_group_autotune(dsmc_group* g, int32_t* tile_mult_out, int32_t* ppb_out,
+                        int32_t* waves_per_cu_out) {
     if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
     if (g->members.empty()) return fail(&g->err, DSMC_ERR_STATE, "group has no members");
     const std::string sig = group_signature(g);
-    int best_tm = 1, best_ppb = 0;
-    if (!tune_lookup(sig, &best_tm, &best_ppb)) {
+    Tuning best{1, 0, 0};
+    if (!tune_lookup(sig, &best)) {
         static const int tms[] = {1, 2, 4};
         static const int ppbs[] = {0, 1024, 4096};
+        static const int wpcs[] = {8, 12, 16};
         hipEvent_t e0, e1;
         HIP_TRY(&g->err, hipEventCreate(&e0));
         HIP_TRY(&g->err, hipEventCreate(&e1));
-        float best = 1e30f;
+        float best_ms = 1e30f;
         int rc = DSMC_OK;
         for (int tm : tms) {
             for (int pb : ppbs) {
-                g->tile_mult = tm;
-                g->ppb = pb;
-                g->dirty = true;
-                rc = enqueue_steps(g, 1);
-                if (rc) break;
-                (void)hipEventRecord(e0, g->stream);
-                rc = enqueue_steps(g, 3);
-                if (rc) break;
-                (void)hipEventRecord(e1, g->stream);
-                if (hipEventSynchronize(e1) != hipSuccess) {
-                    rc = fail(&g->err, DSMC_ERR_DEVICE, "event synchronise failed");
-                    break;
-                }
                 float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best) {
-                    best = ms;
-                    best_tm = tm;
-                    best_ppb = pb;
+                const Tuning t{tm, pb, 0};
+                rc = time_shape(g, t, e0, e1, &ms);
+                if (rc) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
                 }
             }
             if (rc) break;
+        }
+        if (!rc) {
+            const Tuning pair = best;
+            for (int w : wpcs) {
+                float ms = 0.f;
+                const Tuning t{pair.tile_mult, pair.ppb, w};
+                rc = time_shape(g, t, e0, e1, &ms);
+                if (rc) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         for (dsmc_handle* h : g->members) h->sorted = true;
         if (rc) return rc;
-        tune_store(sig, best_tm, best_ppb);
+        tune_store(sig, best);
     }
-    g->tile_mult = best_tm;
-    g->ppb = best_ppb;
+    g->tile_mult = best.tile_mult;
+    g->ppb = best.ppb;
+    g->waves_per_cu = best.waves_per_cu;
     g->dirty = true;
-    if (tile_mult_out) *tile_mult_out = best_tm;
-    if (ppb_out) *ppb_out = best_ppb;
+    if (tile_mult_out) *tile_mult_out = best.tile_mult;
+    if (ppb_out) *ppb_out = best.ppb;
+    if (waves_per_cu_out) *waves_per_cu_out = best.waves_per_cu;
     return DSMC_OK;
 }
 

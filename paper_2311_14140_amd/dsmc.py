@@ -100,9 +100,9 @@ def _load():
                             ct.POINTER(ct.c_double)],
         "dsmc_set_open_state": [vp, i32, i64, i64, ct.c_double],
         "dsmc_group_destroy": [vp],
-        "dsmc_group_set_tuning": [vp, i32, i32],
+        "dsmc_group_set_tuning": [vp, i32, i32, i32],
         "dsmc_group_set_resident": [vp, i32],
-        "dsmc_group_autotune": [vp, ct.POINTER(i32), ct.POINTER(i32)],
+        "dsmc_group_autotune": [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)],
         "dsmc_profile_step": [vp, i64, vp],
     }
     for name, args in sig.items():
@@ -372,8 +372,9 @@ class Group:
         _check(lib.dsmc_group_lanes(self._g, ct.byref(n)))
         return n.value
 
-    def set_tuning(self, tile_mult: int = 0, particles_per_block: int = 0):
-        _check(lib.dsmc_group_set_tuning(self._g, int(tile_mult), int(particles_per_block)))
+    def set_tuning(self, tile_mult: int = 0, particles_per_block: int = 0, waves_per_cu: int = 0):
+        _check(lib.dsmc_group_set_tuning(self._g, int(tile_mult), int(particles_per_block),
+                                         int(waves_per_cu)))
 
     def set_resident(self, enable: bool = True):
         """Step small members in one workgroup each (the default) or with the
@@ -381,9 +382,11 @@ class Group:
         _check(lib.dsmc_group_set_resident(self._g, 1 if enable else 0))
 
     def autotune(self):
-        a, b = ct.c_int32(), ct.c_int32()
-        _check(lib.dsmc_group_autotune(self._g, ct.byref(a), ct.byref(b)))
-        return a.value, b.value
+        """Tune the launch shape on the group's own steps; returns
+        (tile_mult, particles_per_block, waves_per_cu)."""
+        a, b, c = ct.c_int32(), ct.c_int32(), ct.c_int32()
+        _check(lib.dsmc_group_autotune(self._g, ct.byref(a), ct.byref(b), ct.byref(c)))
+        return a.value, b.value, c.value
 
     def close(self):
         if getattr(self, "_g", None) is not None and self._g.value:

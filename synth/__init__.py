@@ -75,10 +75,11 @@ CONFIG1 = Params(kn=0.1, body_force=0.005, n_cells=300, particles_per_cell=1000,
 CONFIG1_STEPS = 21000
 
 # Large near-continuum instance: Kn = 0.01, 1000 cells x 20000 per cell (2e7
-# particles), 1000 transient + 10000 sampling steps.  Collision sub-cells keep a
-# collision cell small enough to stage on chip.
+# particles), 1000 transient + 10000 sampling steps.  Two collision sub-cells per
+# sampling cell (10^4 particles, 0.05 lambda wide) keep a collision cell small
+# enough to stage on chip.
 CONFIG2 = Params(kn=0.01, body_force=0.001, n_cells=1000, particles_per_cell=20000,
-                 n_transient=1000, seed=seed_of(2), precision=FP32_FAST, n_sub=4)
+                 n_transient=1000, seed=seed_of(2), precision=FP32_FAST, n_sub=2)
 CONFIG2_STEPS = 11000
 
 

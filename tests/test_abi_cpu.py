@@ -98,7 +98,8 @@ def test_null_safety(D):
     assert D.lib.dsmc_params_init(None) == D.DSMC_ERR_INVALID_ARG
     assert D.lib.dsmc_group_create(None, None) == D.DSMC_ERR_INVALID_ARG
     assert D.lib.dsmc_group_set_resident(None, 1) == D.DSMC_ERR_INVALID_ARG
-    assert D.lib.dsmc_group_set_tuning(None, 0, 0) == D.DSMC_ERR_INVALID_ARG
+    assert D.lib.dsmc_group_set_tuning(None, 0, 0, 0) == D.DSMC_ERR_INVALID_ARG
+    assert D.lib.dsmc_group_autotune(None, None, None, None) == D.DSMC_ERR_INVALID_ARG
     assert D.lib.dsmc_set_inflow(None, 0.0, 0.0, 1.0, 1.0) == D.DSMC_ERR_INVALID_ARG
     assert D.lib.dsmc_open_state(None, None, None, None, None) == D.DSMC_ERR_INVALID_ARG
     for code in (0, -1, -2, -3, -4, -5):

@@ -238,12 +238,12 @@ def test_instance_alone_equals_in_group(D, prec_name):
 def test_launch_shape_does_not_change_results(D):
     ps = _mix(D, D.DSMC_FP32_FAST)
     results = []
-    for tile_mult, ppb in ((0, 0), (2, 3000), (4, 8192)):
+    for tile_mult, ppb, wpc in ((0, 0, 0), (2, 3000, 8), (4, 8192, 12)):
         g = D.Group()
         sols = [D.Solver(p) for p in ps]
         for s in sols:
             g.add(s)
-        g.set_tuning(tile_mult, ppb)
+        g.set_tuning(tile_mult, ppb, wpc)
         g.step(17)
         g.sync()
         results.append([(s.get_state(), s.sample(raw=True)["raw"]) for s in sols])
@@ -297,15 +297,18 @@ def test_autotune_choice_valid_and_results_unchanged(D):
     ref = []
     for p in ps:
         with D.Solver(p) as s:
-            s.step(40)
+            s.step(52)
             ref.append(s.get_state())
     g = D.Group()
     sols = [D.Solver(p) for p in ps]
     for s in sols:
         g.add(s)
-    tm, ppb = g.autotune()          # runs 36 real steps
-    assert tm in (1, 2, 4) and ppb in (0, 1024, 4096)
-    assert g.autotune() == (tm, ppb)  # cached per group shape: no further steps
+    # 9 (tile, cells-per-block) pairs, then 3 occupancy caps: 12 shapes of 4
+    # real steps each
+    choice = g.autotune()
+    tm, ppb, wpc = choice
+    assert tm in (1, 2, 4) and ppb in (0, 1024, 4096) and wpc in (0, 8, 12, 16)
+    assert g.autotune() == choice  # cached per group shape: no further steps
     g.step(4)
     g.sync()
     for s, r in zip(sols, ref):
