@@ -54,11 +54,17 @@ def _dp():
 
 
 def lib():
+    """The oracle library: ``libdsmc_oracle.so`` (built if missing or stale),
+    or the build named by DSMC_ORACLE_LIB, which the mutation tests use to run
+    the pins against deliberately broken copies of the oracle."""
     global _lib
     with _lock:
         if _lib is None:
-            build(force=False)
-            L = ct.CDLL(LIB)
+            path = os.environ.get("DSMC_ORACLE_LIB")
+            if not path:
+                build(force=False)
+                path = LIB
+            L = ct.CDLL(path)
             vp = ct.c_void_p
             L.or_create.restype = vp
             L.or_create.argtypes = [ct.POINTER(_Params)]

@@ -132,22 +132,19 @@ def _mean_se(batches, key):
     return a.mean(0), a.std(0, ddof=1) / math.sqrt(len(a))
 
 
-def test_cauchy_stress_is_linear_at_any_kn(cfg0_batches):
+def test_cauchy_stress_line_cell_by_cell(cfg0_batches):
+    """Config 0 (Kn = 1, F = 0.01): in every cell the time-centred stress
+    P_xy (the P^DSMC of Eq. 13) sits on the line 2F (y - 1/2) that the
+    momentum balance of Eq. 1 gives, within its batch standard error.  The
+    slope itself is pinned to 1% by the replica test below."""
     F = CONFIG0.body_force
     C = CONFIG0.n_cells
     yc = (np.arange(C) + 0.5) / C
-    m, se = _mean_se(cfg0_batches, "pxy")
+    m, se = _mean_se(cfg0_batches, "pxy_mid")
     want = 2.0 * F * (yc - 0.5)
     z = (m - want) / se
     assert np.mean(z**2) < 1.6, np.mean(z**2)
     assert np.max(np.abs(z)) < 4.5
-    # weighted straight-line fit: slope 2F, zero at the centre
-    w = 1 / se**2
-    A = np.stack([np.ones(C), yc - 0.5], 1)
-    cov = np.linalg.inv(A.T @ (A * w[:, None]))
-    coef = cov @ (A.T @ (w * m))
-    assert abs(coef[1] - 2 * F) < 3.5 * math.sqrt(cov[1, 1]) + 0.02 * 2 * F
-    assert abs(coef[0]) < 3.5 * math.sqrt(cov[0, 0])
 
 
 def test_profiles_symmetric_about_centre(cfg0_batches):
@@ -218,43 +215,48 @@ def test_pre_collision_stress_sum_is_taken_before_the_collide_phase():
     assert np.allclose(after[:, 0] - before[:, 0], count)
 
 
-def _stress_slopes(seed, dt):
-    """Interior (4 cells from each plate excluded) least-squares slopes of
-    the post-collision and time-centred stresses over 2F, with their
-    standard errors, for a Kn = 1 channel sampled 30000 steps."""
+def _stress_slopes(seed, kn):
+    """Least-squares slope (over 2F) and centre value of the post-collision
+    and time-centred stresses of a channel at ``kn`` with F = 0.05, 40 cells
+    of 100 particles, sampled 30000 steps; cells within 0.1 of a plate are
+    left out."""
     C, F = 40, 0.05
-    p = Params(kn=1.0, body_force=F, n_cells=C, particles_per_cell=100, n_transient=300,
-               seed=seed, dt=dt)
+    p = Params(kn=kn, body_force=F, n_cells=C, particles_per_cell=100, n_transient=300,
+               seed=seed)
     o = oracle.Oracle(p)
     o.step(30300)
     e = o.estimators()
     y = (np.arange(C) + 0.5) / C
-    sl = slice(4, C - 4)
-    A = np.vstack([y[sl] - 0.5, np.ones(C - 8)]).T
+    sel = (y > 0.1) & (y < 0.9)
     out = {}
     for k in ("pxy", "pxy_mid"):
-        co = np.linalg.lstsq(A, e[k][sl], rcond=None)[0]
-        r = e[k][sl] - A @ co
-        se = math.sqrt((r @ r) / (len(r) - 2) / np.sum((y[sl] - 0.5) ** 2))
-        out[k] = (co[0] / (2 * F), se / (2 * F))
+        slope, centre = np.polyfit(y[sel] - 0.5, e[k][sel], 1)
+        out[k] = (slope / (2 * F), centre)
     return out, o.constants()["dt"]
 
 
-def test_time_centred_stress_keeps_the_momentum_balance():
-    """Steady force-driven flow has dP/dy = 2F (Eqs. 1 and 6).  The stress
-    sampled after the collisions misses it by a first-order amount: the
-    collisions relax the stress by about dt / tau_p, tau_p = mu / p, and the
-    estimate lies about half of that below the flux of the free flights,
-    0.089 at the default step of a hard-sphere gas.  The mean of the
-    estimates before and after the collisions meets the balance."""
-    from concurrent.futures import ThreadPoolExecutor
-    with ThreadPoolExecutor(2) as ex:
-        (a, dt), (b, _) = list(ex.map(lambda s: _stress_slopes(s, 0.0), (11, 12)))
-    # mu / p in units of H / sqrt(kT/m) at Kn = 1: the hard-sphere viscosity
-    # (Chapman and Cowling, with its higher-order factor 1.016) is
-    # mu = 1.016 (5/8) sqrt(pi) Kn P0 H / v0, and v0 = sqrt(2)
-    tau_p = 1.016 * 0.625 * math.sqrt(math.pi) / math.sqrt(2.0)
+@pytest.mark.parametrize("kn", [1.0, 0.2])
+def test_stress_slope_meets_the_momentum_balance_at_any_kn(kn):
+    """Steady force-driven flow has dP/dy = 2F whatever the Knudsen number
+    (Eq. 1, the balance the paper calls always correct, in the units of
+    Eq. 6), and P = 0 at the centre by symmetry.  The time-centred stress
+    meets the slope to 1%: its second-order residual is a few tenths of a
+    percent at the default step.  The stress sampled after the collisions
+    lies below the free-flight flux by half of the relaxation dt / tau_p the
+    collisions apply, tau_p = mu / p = 1.016 (5/16) sqrt(2 pi) lambda for
+    hard spheres (Chapman and Cowling, with the higher-order factor), so its
+    slope is 1 - dt / (2 tau_p) = 0.911 at dt = 0.2 lambda / sqrt(2).  Eight
+    independent replicas per Kn give the spread; the slope's standard error
+    is below 0.001, so a 3% error in the stress fails by over 20 of them."""
+    with ThreadPoolExecutor(8) as ex:
+        runs = list(ex.map(lambda s: _stress_slopes(s, kn), range(300, 308)))
+    dt = runs[0][1]
+    tau_p = 1.016 * (5.0 / 16.0) * math.sqrt(2.0 * math.pi) * kn
     for k, want in (("pxy", 1.0 - 0.5 * dt / tau_p), ("pxy_mid", 1.0)):
-        slope = 0.5 * (a[k][0] + b[k][0])
-        se = 0.5 * math.hypot(a[k][1], b[k][1])
-        assert abs(slope - want) < 4 * se + 0.005, (k, slope, want, se)
+        slopes = np.array([r[0][k][0] for r in runs])
+        centres = np.array([r[0][k][1] for r in runs])
+        se = slopes.std(ddof=1) / math.sqrt(len(slopes))
+        assert se < 0.002, (k, se)
+        assert abs(slopes.mean() - want) < 0.01, (k, slopes.mean(), want, se)
+        se_c = centres.std(ddof=1) / math.sqrt(len(centres))
+        assert abs(centres.mean()) < 5 * se_c + 1e-5, (k, centres.mean(), se_c)
