@@ -268,6 +268,22 @@ int dsmc_group_size(const dsmc_group *g, int32_t *n_members);
  * first such member.  INVALID_ARG for a wrong n_outs, a too-small n_cells or
  * non-NULL raw_sums. */
 int dsmc_group_sample(dsmc_group *g, dsmc_moments *outs, int32_t n_outs, int reset_window);
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): dsmc_group_sample with
+ * the same arguments, results and errors, which calls no hipMalloc, hipFree
+ * or other allocating routine.  Its descriptor table, offsets and device
+ * staging live in one fixed 32 MiB device array of the library (each GPU
+ * holds its own copy until the process ends), and the host side of the
+ * staging in a fixed host array; nothing is kept with the group.  Limits:
+ * at most 1024 members, and the members' estimators (9 n_cells + 4 doubles
+ * each, rounded up to 32) within 32 MiB less 16 KiB; beyond them INVALID_ARG
+ * and nothing is done.  The current HIP device must be the group's.  Calls
+ * in one process are serialised by a lock and each synchronises the group's
+ * stream before it returns, so the array keeps the last call's contents;
+ * every value read back is written by the call itself.  Calls that overlap
+ * on one GPU from outside that lock would race on the array. */
+int dsmc_group_sample_noalloc(dsmc_group *g, dsmc_moments *outs, int32_t n_outs,
+                              int reset_window);
 /* Lanes the members were split into at the last step: a group of at least
  * 2e6 particles and two or more members runs in two lanes (each with its own
  * stream, work lists and step graph, forked from and joined back to the

@@ -2144,12 +2144,32 @@ __global__ __launch_bounds__(256) void k_finalize_staged(const InstDesc* __restr
     if (threadIdx.x == 0) est[kEstPerCell * d.C + 3] = (double)d.sc->status;
 }
 
-__global__ __launch_bounds__(256) void k_reset_window(const InstDesc* __restrict__ descs) {
-    const InstDesc& d = descs[blockIdx.x];
+// The same from a table of pointers to the instances' own device
+// descriptors, so that no descriptor array has to be built for the call.
+__global__ __launch_bounds__(256) void k_finalize_gather(const InstDesc* const* __restrict__ descs,
+                                                        const int64_t* __restrict__ off,
+                                                        double* __restrict__ stage) {
+    __shared__ double col[kFinalizeChunk];
+    __shared__ unsigned long long coll_part[256];
+    const InstDesc& d = *descs[blockIdx.x];
+    double* est = stage + off[blockIdx.x];
+    finalize_into(d, est, col, coll_part);
+    if (threadIdx.x == 0) est[kEstPerCell * d.C + 3] = (double)d.sc->status;
+}
+
+__device__ __forceinline__ void reset_window_of(const InstDesc& d) {
     const size_t n = (size_t)d.Cc * kMoments;
     for (size_t i = threadIdx.x; i < n; i += blockDim.x) d.acc[i] = 0.0;
     for (int c = threadIdx.x; c < d.Cc; c += blockDim.x) d.ncoll[c] = 0u;
     if (threadIdx.x == 0) d.sc->n_sampled = 0;
+}
+
+__global__ __launch_bounds__(256) void k_reset_window(const InstDesc* __restrict__ descs) {
+    reset_window_of(descs[blockIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void k_reset_window_gather(const InstDesc* const* __restrict__ descs) {
+    reset_window_of(*descs[blockIdx.x]);
 }
 
 // The kernels of one step under a debug phase mask (a move without the sort,
@@ -2381,6 +2401,15 @@ void launch_finalize_staged(const InstDesc* d_desc, const int64_t* d_off, double
 
 void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_window, dim3(n_inst), dim3(256), 0, s, d_desc);
+}
+
+void launch_finalize_gather(const InstDesc* const* d_descs, const int64_t* d_off, double* d_stage,
+                            int n_inst, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_gather, dim3(n_inst), dim3(256), 0, s, d_descs, d_off, d_stage);
+}
+
+void launch_reset_window_gather(const InstDesc* const* d_descs, int n_inst, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset_window_gather, dim3(n_inst), dim3(256), 0, s, d_descs);
 }
 
 }  // namespace dsmc

@@ -58,6 +58,10 @@ void launch_finalize(const InstDesc* d_desc, int n_inst, hipStream_t s);
 void launch_finalize_staged(const InstDesc* d_desc, const int64_t* d_off, double* d_stage,
                             int n_inst, hipStream_t s);
 void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s);
+// The same two from a device table of pointers to each instance's descriptor.
+void launch_finalize_gather(const InstDesc* const* d_descs, const int64_t* d_off, double* d_stage,
+                            int n_inst, hipStream_t s);
+void launch_reset_window_gather(const InstDesc* const* d_descs, int n_inst, hipStream_t s);
 size_t fast_collide_lds_bytes(Mode mode, int cap);
 size_t bucket_collide_lds_bytes(Mode mode, int cap);
 size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max);

@@ -888,6 +888,50 @@ int unpack_group_sample(dsmc_group* g, dsmc_moments* outs, const double* stage, 
     return rc;
 }
 
+// ------------------------------------------------- allocation-free sampling
+// dsmc_group_sample_noalloc keeps its tables and staging in a fixed device
+// array instead of buffers allocated per group: a table of pointers to the
+// members' device descriptors, each member's offset in the staging area, and
+// the staging area itself.  Each device holds its own copy of the array (at
+// its own address, looked up once per device) until the process ends.
+constexpr int kScratchMaxMembers = 1024;
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr size_t kScratchTableBytes = (size_t)kScratchMaxMembers * (sizeof(void*) + sizeof(int64_t));
+constexpr size_t kScratchStageDoubles = (kScratchBytes - kScratchTableBytes) / sizeof(double);
+constexpr int kScratchDevices = 64;
+static_assert(kScratchTableBytes % 256 == 0, "the staging area starts 256-byte aligned");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchDevices] = {};   // scratch's address on each device
+// host side of the staging area: one copy brings every member's block back
+double g_scratch_host[kScratchStageDoubles];
+
+// The current device's address of the scratch array (looked up on the first
+// call on that device).  Call with g_scratch_mu held.
+int scratch_address(std::string* err, char** out) {
+    int dev = -1;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(err, DSMC_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(err, DSMC_ERR_DEVICE, "device index beyond the scratch table");
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t r = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (r != hipSuccess || !ptr)
+            return fail(err, DSMC_ERR_DEVICE,
+                        std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(r));
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = (char*)g_scratch_dev[dev];
+    return DSMC_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -1423,6 +1467,55 @@ int dsmc_group_sample(dsmc_group* g, dsmc_moments* outs, int32_t n_outs, int res
     }
     HIP_TRY(&g->err, hipStreamSynchronize(s));
     return unpack_group_sample(g, outs, g->h_stage, g->soff.data());
+}
+
+int dsmc_group_sample_noalloc(dsmc_group* g, dsmc_moments* outs, int32_t n_outs, int reset_window) {
+    if (!g || (!outs && n_outs)) return fail(g ? &g->err : nullptr, DSMC_ERR_INVALID_ARG, "NULL argument");
+    const int n = (int)g->members.size();
+    if (n_outs != n) return fail(&g->err, DSMC_ERR_INVALID_ARG, "n_outs differs from the group's member count");
+    if (n == 0) return DSMC_OK;
+    if (n > kScratchMaxMembers)
+        return fail(&g->err, DSMC_ERR_INVALID_ARG,
+                    "dsmc_group_sample_noalloc: more than 1024 members (use dsmc_group_sample)");
+    for (int i = 0; i < n; ++i) {
+        if (outs[i].n_cells < g->members[i]->plan.C)
+            return fail(&g->err, DSMC_ERR_INVALID_ARG, "moments.n_cells smaller than a member's cells");
+        if (outs[i].raw_sums)
+            return fail(&g->err, DSMC_ERR_INVALID_ARG, "raw sums are returned by dsmc_sample only");
+    }
+    // the descriptor table and the staging offsets, on the host stack
+    const InstDesc* ptrs[kScratchMaxMembers];
+    int64_t offs[kScratchMaxMembers];
+    size_t tot = 0;
+    for (int i = 0; i < n; ++i) {
+        ptrs[i] = g->members[i]->d_desc;
+        offs[i] = (int64_t)tot;
+        tot += ((size_t)kEstPerCell * g->members[i]->plan.C + 4 + 31) & ~(size_t)31;
+    }
+    if (tot > kScratchStageDoubles)
+        return fail(&g->err, DSMC_ERR_INVALID_ARG,
+                    "dsmc_group_sample_noalloc: the members' estimators exceed the 32 MiB "
+                    "scratch (use dsmc_group_sample)");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    char* base = nullptr;
+    int r = scratch_address(&g->err, &base);
+    if (r) return r;
+    const InstDesc** d_ptrs = (const InstDesc**)base;
+    int64_t* d_offs = (int64_t*)(base + (size_t)kScratchMaxMembers * sizeof(void*));
+    double* d_stage = (double*)(base + kScratchTableBytes);
+    hipStream_t s = g->stream;
+    HIP_TRY(&g->err, hipMemcpyAsync(d_ptrs, ptrs, sizeof(void*) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(&g->err, hipMemcpyAsync(d_offs, offs, sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+    launch_finalize_gather(d_ptrs, d_offs, d_stage, n, s);
+    HIP_TRY(&g->err, hipGetLastError());
+    HIP_TRY(&g->err, hipMemcpyAsync(g_scratch_host, d_stage, tot * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (reset_window) {
+        launch_reset_window_gather(d_ptrs, n, s);
+        HIP_TRY(&g->err, hipGetLastError());
+    }
+    // the stack tables above must outlive the copies that read them
+    HIP_TRY(&g->err, hipStreamSynchronize(s));
+    return unpack_group_sample(g, outs, g_scratch_host, offs);
 }
 
 int dsmc_group_size(const dsmc_group* g, int32_t* n) {

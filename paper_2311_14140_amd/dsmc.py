@@ -38,7 +38,7 @@ EXPORTS = (
     "dsmc_group_sync", "dsmc_group_size", "dsmc_group_lanes", "dsmc_group_destroy", "dsmc_group_set_tuning",
     "dsmc_group_set_resident",
     "dsmc_group_autotune", "dsmc_profile_step", "dsmc_group_sample", "dsmc_set_inflow",
-    "dsmc_open_state", "dsmc_set_open_state",
+    "dsmc_open_state", "dsmc_set_open_state", "dsmc_group_sample_noalloc",
 )
 
 
@@ -95,6 +95,7 @@ def _load():
         "dsmc_group_size": [vp, ct.POINTER(i32)],
         "dsmc_group_lanes": [vp, ct.POINTER(i32)],
         "dsmc_group_sample": [vp, vp, i32, ct.c_int],
+        "dsmc_group_sample_noalloc": [vp, vp, i32, ct.c_int],
         "dsmc_set_inflow": [vp, ct.c_double, ct.c_double, ct.c_double, ct.c_double],
         "dsmc_open_state": [vp, ct.POINTER(i32), ct.POINTER(i64), ct.POINTER(i64),
                             ct.POINTER(ct.c_double)],
@@ -344,10 +345,12 @@ class Group:
     def sync(self):
         _check(lib.dsmc_group_sync(self._g))
 
-    def sample(self, reset: bool = False) -> list:
+    def sample(self, reset: bool = False, noalloc: bool = False) -> list:
         """Every member's window estimators (as ``Solver.sample`` without raw
         sums), in member order, with one launch, one copy and one
-        synchronisation for the whole group."""
+        synchronisation for the whole group.  ``noalloc`` takes them through
+        the library's allocation-free variant (fixed scratch, at most 1024
+        members and 32 MiB of estimators)."""
         n = len(self.members)
         ms = (dsmc_moments * max(n, 1))()
         outs = []
@@ -358,7 +361,8 @@ class Group:
             for k, a in arrs.items():
                 setattr(ms[i], k, a.ctypes.data_as(_dp))
             outs.append(arrs)
-        _check(lib.dsmc_group_sample(self._g, ms, n, 1 if reset else 0))
+        fn = lib.dsmc_group_sample_noalloc if noalloc else lib.dsmc_group_sample
+        _check(fn(self._g, ms, n, 1 if reset else 0))
         for i, arrs in enumerate(outs):
             arrs["mass_flow"] = ms[i].mass_flow
             arrs["n_sampled_steps"] = ms[i].n_sampled_steps
