@@ -40,7 +40,7 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 QUANTITIES = ("n", "ux", "T", "pxy", "qx")
-MIX_TRANSIENT, MIX_SAMPLING, MIX_BINS = 100, 300, 16
+MIX_TRANSIENT, MIX_SAMPLING, MIX_BINS = 100, 1000, 16
 
 SCHEDULES = {
     # workload: (params, workload index for seeds, transient, sampling steps)
@@ -90,14 +90,15 @@ def main_mix(args):
             for name in QUANTITIES:
                 out[name][i, r] = prof[name]
             Q[i, r] = q
-            if n % 64 == 63 or n == len(jobs) - 1:
+            if n % 16 == 15 or n == len(jobs) - 1:
                 print(f"{n + 1}/{len(jobs)} runs ({time.time() - t0:.0f} s)", flush=True)
     src = open(oracle.SRC, "rb").read()
     meta = dict(workload="cfg3", instances=len(inst), transient=MIX_TRANSIENT,
                 sampling_steps=MIX_SAMPLING, bins=MIX_BINS, replicas=args.replicas,
                 first_replica=args.first, seed_rule="synth.seed_of(3, i, r)",
                 mix="synth.config3_instances()", oracle_sha256=hashlib.sha256(src).hexdigest())
-    path = os.path.join(HERE, f"oracle_cfg3_mix_r{args.first}_{args.first + args.replicas}.npz")
+    path = os.path.join(args.out or HERE, f"oracle_cfg3_mix_s{MIX_SAMPLING}_r{args.first}_"
+                                          f"{args.first + args.replicas}.npz")
     np.savez_compressed(path, mass_flow=Q, **out, meta=json.dumps(meta))
     print("wrote", path, flush=True)
 
@@ -108,6 +109,7 @@ def main():
     ap.add_argument("--replicas", type=int, default=64)
     ap.add_argument("--workers", type=int, default=max(1, (os.cpu_count() or 2) - 2))
     ap.add_argument("--first", type=int, default=0, help="index of the first replica")
+    ap.add_argument("--out", default=None, help="directory of the written file (default: here)")
     args = ap.parse_args()
     if args.workload == "cfg3":
         return main_mix(args)
