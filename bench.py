@@ -64,18 +64,14 @@ def kernel_bytes(phase: str, N: int, Cc: int, rb: int, coll_frac: float, samplin
 PROFILE_TAGS = {"cfg1": "kernels_cfg1_kn0.1_300x1000_fp32",
                 "cfg2": "kernels_cfg2_kn0.01_1000x20000_fp32",
                 "cfg3": "kernels_cfg3_batched256_fp32"}
-# sources whose change invalidates the committed counters: the kernels and the
-# runtime that chooses their launch shapes
-TRAFFIC_SOURCES = ("kernels.hip", "runtime.hip", "rng.hpp", "common.hpp", "kernels.hpp")
 
 
 def kernel_source_hash() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_2311_14140_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the kernels and of the runtime that chooses their launch
+    shapes: the committed counters hold only for the sources they were
+    taken with."""
+    from paper_2311_14140_amd.rocprof_summary import source_hash
+    return source_hash()
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -117,8 +113,14 @@ class Subject:
         return self.sols[0].profile(n)
 
     def lanes(self):
-        # each kernel of a step is launched once per lane of the group
-        return self.group.lanes() if self.group else 1
+        """(multi-kernel lanes, particles and collision cells in them): each
+        multi-kernel phase of a step is launched once per such lane; members
+        small enough run resident in a lane of their own."""
+        if not self.group:
+            return 1, self.N, self.Cc
+        li = self.group.lane_info()
+        return (li["lanes"] - li["resident_lanes"], self.N - li["resident_particles"],
+                self.Cc - li["resident_cells"])
 
     def sample(self):
         return [s.sample(reset=True) for s in self.sols]
@@ -392,9 +394,20 @@ def main():
     bucketed = rb == 4 and all(p.particles_per_cell / p.n_sub < 256 for p in plist)
     # per launch: a step launches each kernel once per lane, on that lane's
     # share of the particles (the profiler's dispatches are these launches)
-    lanes = sub.lanes()
-    dom_bytes = kernel_bytes(dom, N, Cc, rb, coll_frac, True, bucketed) / lanes
-    dom_ms = kern[dom] / lanes
+    lanes, n_multi, cc_multi = sub.lanes()
+    resident_note = None
+    dom_total_ms = kern[dom]
+    if n_multi != N:
+        # small members run resident in a lane of their own, whose whole step
+        # is one kernel timed in the collide slot: the dominant kernel's
+        # figures cover the multi-kernel lanes only
+        resident_note = (f"{N - n_multi} particles of small members stepped resident in a lane "
+                         f"of their own ({prof['resident'] / args.profile_steps:.4f} ms/step); "
+                         f"per-launch figures cover the other {n_multi}")
+        if dom == "collide":
+            dom_total_ms -= prof["resident"] / args.profile_steps
+    dom_bytes = kernel_bytes(dom, n_multi, cc_multi, rb, coll_frac, True, bucketed) / max(lanes, 1)
+    dom_ms = dom_total_ms / max(lanes, 1)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     step_bytes = sum(kernel_bytes(k, N, Cc, rb, coll_frac, True, bucketed) for k in kern)
     log("per-kernel ms/step: " + ", ".join(f"{k}={v:.4f}" for k, v in kern.items()))
@@ -508,7 +521,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload, dom), "kernel_ms": dom_ms,
-                     "algorithmic_bytes_per_launch": dom_bytes, "launches_per_step": lanes},
+                     "algorithmic_bytes_per_launch": dom_bytes, "launches_per_step": lanes,
+                     "note": resident_note},
         "step_roofline": {"algorithmic_bytes_per_step": step_bytes,
                           "achieved_GBps": step_bytes / (el / args.steps) / 1e9,
                           "frac": step_bytes / (el / args.steps) / 1e9 / HBM_PEAK_GBS,

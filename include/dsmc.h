@@ -227,9 +227,11 @@ int dsmc_info(const dsmc_handle *h, int32_t *n_particles, int32_t *n_coll_cells,
 
 /* Per-phase timing: run n_steps >= 1 steps of the handle (real steps, launched
  * one kernel at a time on its stream) with HIP events around every kernel and
- * write the summed device milliseconds of each kernel to phase_ms[8] (host):
+ * write the summed device milliseconds of each kernel to phase_ms[9] (host):
  * move+histogram, column sums, scan, column prefix, scatter, collide+sample,
- * and [6] = all kernels, [7] = wall time of the whole run.  Synchronises. */
+ * and [6] = all kernels, [7] = wall time of the whole run, [8] = the part of
+ * the collide slot spent in resident lanes (whose whole step is one kernel,
+ * counted in the collide slot).  Synchronises. */
 int dsmc_profile_step(dsmc_handle *h, int64_t n_steps, double *phase_ms);
 
 const char *dsmc_status_string(int status);
@@ -290,6 +292,14 @@ int dsmc_group_sample_noalloc(dsmc_group *g, dsmc_moments *outs, int32_t n_outs,
  * group's stream), so each of a step's kernels is launched once per lane.
  * Results do not depend on it. */
 int dsmc_group_lanes(const dsmc_group *g, int32_t *n_lanes);
+/* The lanes of the last step in more detail: all lanes, those stepped
+ * resident, and the nominal particles and collision cells of the members in
+ * resident lanes (any pointer may be NULL).  A group that mixes members small enough to run
+ * resident (see dsmc_group_set_resident) with larger ones steps the small
+ * ones in a lane of their own, beside the multi-kernel lanes of the others,
+ * so a step launches the multi-kernel phases once per multi-kernel lane. */
+int dsmc_group_lane_info(const dsmc_group *g, int32_t *n_lanes, int32_t *resident_lanes,
+                         int64_t *resident_particles, int64_t *resident_cells);
 int dsmc_group_destroy(dsmc_group *g);
 
 /* Launch-shape tuning of a group: tile_mult multiplies each member's base

@@ -255,7 +255,9 @@ __device__ __forceinline__ int flight_from_wall(const InstDesc& d, uint32_t step
 
 // The whole flight of one step as one loop (the same arithmetic as
 // flight_start followed by flight_from_wall).  Returns the number of hits.
-template <class R, bool kOpen>
+// With kVel false only y and vy are followed (vx and vz are left as they
+// are): a re-emission then draws its normal speed alone.
+template <class R, bool kOpen, bool kVel = true>
 __device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32_t slot, R& y,
                                         R& vx, R& vy, R& vz, bool& gone) {
     const R H = (R)d.H, g = (R)d.g, sd = (R)d.sqrt_tw;
@@ -277,7 +279,10 @@ __device__ __forceinline__ int move_one(const InstDesc& d, uint32_t step, uint32
         t = t - tw;
         Stream st(d.key0, d.key1, step, slot, (uint32_t)h, kTagWall);
         R vn;
-        wall_draws<R>(st, sd, vn, vx, vz);
+        if (kVel)
+            wall_draws<R>(st, sd, vn, vx, vz);
+        else
+            vn = wall_normal_speed<R>(st, sd);
         vy = top ? -vn : vn;
         ++h;
     }
@@ -662,7 +667,7 @@ template <class R, bool kOpen>
 __device__ __forceinline__ int flight_key(const InstDesc& d, uint32_t step, uint32_t slot, R y, R vy) {
     R vx = R(0), vz = R(0);
     bool gone = false;
-    move_one<R, kOpen>(d, step, slot, y, vx, vy, vz, gone);
+    move_one<R, kOpen, false>(d, step, slot, y, vx, vy, vz, gone);
     return key_of<R, kOpen>(d, y, gone);
 }
 
@@ -2157,6 +2162,14 @@ __global__ __launch_bounds__(256) void k_finalize_gather(const InstDesc* const* 
     if (threadIdx.x == 0) est[kEstPerCell * d.C + 3] = (double)d.sc->status;
 }
 
+// The status words of n instances into out (one synchronisation and one
+// copy check a whole group).
+__global__ __launch_bounds__(256) void k_gather_status(const InstDesc* __restrict__ descs, int n,
+                                                      int32_t* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = descs[i].sc->status;
+}
+
 __device__ __forceinline__ void reset_window_of(const InstDesc& d) {
     const size_t n = (size_t)d.Cc * kMoments;
     for (size_t i = threadIdx.x; i < n; i += blockDim.x) d.acc[i] = 0.0;
@@ -2401,6 +2414,12 @@ void launch_finalize_staged(const InstDesc* d_desc, const int64_t* d_off, double
 
 void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_window, dim3(n_inst), dim3(256), 0, s, d_desc);
+}
+
+void launch_gather_status(const InstDesc* d_desc, int n_inst, int32_t* d_out, hipStream_t s) {
+    if (n_inst > 0)
+        hipLaunchKernelGGL(k_gather_status, dim3((n_inst + 255) / 256), dim3(256), 0, s, d_desc, n_inst,
+                           d_out);
 }
 
 void launch_finalize_gather(const InstDesc* const* d_descs, const int64_t* d_off, double* d_stage,

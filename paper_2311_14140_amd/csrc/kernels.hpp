@@ -58,6 +58,8 @@ void launch_finalize(const InstDesc* d_desc, int n_inst, hipStream_t s);
 void launch_finalize_staged(const InstDesc* d_desc, const int64_t* d_off, double* d_stage,
                             int n_inst, hipStream_t s);
 void launch_reset_window(const InstDesc* d_desc, int n_inst, hipStream_t s);
+// Status word of each of n_inst instances into d_out.
+void launch_gather_status(const InstDesc* d_desc, int n_inst, int32_t* d_out, hipStream_t s);
 // The same two from a device table of pointers to each instance's descriptor.
 void launch_finalize_gather(const InstDesc* const* d_descs, const int64_t* d_off, double* d_stage,
                             int n_inst, hipStream_t s);

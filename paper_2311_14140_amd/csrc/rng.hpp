@@ -175,6 +175,22 @@ __device__ __forceinline__ void wall_draws<float>(Stream& st, float sd, float& v
     if (!polar_try(x.y, x.z, sd, t0, t1)) normal_pair<float>(st, sd, t0, t1);
 }
 
+// The normal speed of a re-emission alone, from the same words and in the
+// same arithmetic as wall_draws (it never depends on the tangential pair):
+// what a flight of the position alone needs.
+template <class R>
+__device__ __forceinline__ R wall_normal_speed(Stream& st, R sd) {
+    R ua, ub;
+    Num<R>::uni2(st.next(), ua, ub);
+    return Num<R>::sqrt(R(-2) * Num<R>::log(ua)) * sd;
+}
+
+template <>
+__device__ __forceinline__ float wall_normal_speed<float>(Stream& st, float sd) {
+    const uint4 x = st.next();
+    return Num<float>::sqrt(-2.0f * Num<float>::log(u24(x.x))) * sd;
+}
+
 // Marsaglia (1972): uniform point on the unit sphere from a point uniform in
 // the unit disc: (2a sqrt(1-q), 2b sqrt(1-q), 1 - 2q).
 template <class R>

@@ -335,6 +335,7 @@ struct Lane {
     hipStream_t cap_stream = nullptr;
     hipStream_t stream = nullptr;    // own stream when the group has several lanes
     hipEvent_t done = nullptr;
+    int32_t* d_status = nullptr;  // in d_mem: the members' status words (dsmc_group_sync)
 };
 
 struct dsmc_group {
@@ -349,6 +350,7 @@ struct dsmc_group {
     bool resident = true;  // lanes of small instances step them in one workgroup each
     unsigned phase = DSMC_PHASE_ALL;
     int n_lanes = 1;     // lanes in use (lanes.size() may be larger)
+    int resident_lane = -1;  // the lane of the small members of a mixed group, or -1
     std::vector<Lane> lanes;
     hipEvent_t fork = nullptr;
     // dsmc_group_sample: the members' descriptors and staging-block offsets
@@ -592,7 +594,8 @@ int build_lane(dsmc_group* g, Lane& lane) {
     auto bytes_of = [](size_t k, size_t sz) { return align_up(sz * std::max<size_t>(k, 1)); };
     const size_t need = bytes_of(n, sizeof(InstDesc)) + bytes_of(tiles.size(), sizeof(int2)) +
                         bytes_of(cols.size(), sizeof(int4)) + bytes_of(cblocks.size(), sizeof(int4)) +
-                        bytes_of(gblocks.size(), sizeof(int4)) + bytes_of(resident.size(), sizeof(int2));
+                        bytes_of(gblocks.size(), sizeof(int4)) + bytes_of(resident.size(), sizeof(int2)) +
+                        bytes_of(n, sizeof(int32_t));
     if (need > lane.d_bytes) {
         if (lane.d_mem) (void)hipFree(lane.d_mem);
         lane.d_mem = nullptr;
@@ -613,6 +616,8 @@ int build_lane(dsmc_group* g, Lane& lane) {
     int4* d_lb = (int4*)(base + o);
     o += bytes_of(gblocks.size(), sizeof(int4));
     int2* d_res = (int2*)(base + o);
+    o += bytes_of(resident.size(), sizeof(int2));
+    lane.d_status = (int32_t*)(base + o);
     if (n) HIP_TRY(&g->err, hipMemcpy(d_desc, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
     if (!tiles.empty()) HIP_TRY(&g->err, hipMemcpy(d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice));
     if (!cols.empty()) HIP_TRY(&g->err, hipMemcpy(d_cols, cols.data(), sizeof(int4) * cols.size(), hipMemcpyHostToDevice));
@@ -677,6 +682,21 @@ int capture_lane(dsmc_group* g, Lane& l) {
 
 // (Re)build the lanes of a group: members are dealt to the lanes largest
 // first, each to the lane with the fewest particles so far.
+// A member small enough for a resident lane (the conditions build_lane
+// checks for a lane to run resident).
+bool resident_eligible(const dsmc_group* g, const dsmc_handle* h) {
+    if (!g->resident || g->mode == kFp64Det || g->phase != DSMC_PHASE_ALL) return false;
+    if (!((double)h->plan.N / (double)h->plan.Cc < (double)kCoopMin)) return false;
+    if (h->plan.Cc + h->plan.open > kResidentKeys) return false;
+    if (h->plan.ncap > resident_slots((Mode)g->mode)) return false;
+    return resident_lds_bytes((Mode)g->mode, (h->plan.ncap + 63) / 64 * 64) <= (size_t)resident_max_lds();
+}
+
+// (Re)build the lanes of a group.  Members are dealt to the lanes largest
+// first, each to the lane with the fewest particles so far.  A group that
+// mixes members small enough to run resident with larger ones gives the
+// small ones a lane of their own, which steps them resident beside the
+// multi-kernel lanes of the others.
 int rebuild(dsmc_group* g) {
     // the streams may still be running the previous graphs and lists: wait
     // for them before either is released
@@ -684,11 +704,20 @@ int rebuild(dsmc_group* g) {
     for (Lane& l : g->lanes)
         if (l.stream) HIP_TRY(&g->err, hipStreamSynchronize(l.stream));
     drop_graphs(g);
+    g->phase = (g->solo && g->members.size() == 1 && g->members[0]->p.debug_phase_mask)
+                   ? g->members[0]->p.debug_phase_mask
+                   : (unsigned)DSMC_PHASE_ALL;
+    std::vector<dsmc_handle*> small, large;
+    for (dsmc_handle* h : g->members) (resident_eligible(g, h) ? small : large).push_back(h);
+    const bool split = !g->solo && !small.empty() && !large.empty();
+    const std::vector<dsmc_handle*>& multi = split ? large : g->members;
     int64_t total = 0;
-    for (const dsmc_handle* h : g->members) total += h->plan.N;
-    const int nl = (!g->solo && g->members.size() >= 2 && total >= kLaneMinParticles) ? kMaxLanes : 1;
+    for (const dsmc_handle* h : multi) total += h->plan.N;
+    const int nm = (!g->solo && multi.size() >= 2 && total >= kLaneMinParticles) ? kMaxLanes : 1;
+    const int nl = nm + (split ? 1 : 0);
     if ((int)g->lanes.size() < nl) g->lanes.resize(nl);
     g->n_lanes = nl;
+    g->resident_lane = split ? nm : -1;
     if (nl > 1 && !g->fork) HIP_TRY(&g->err, hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
     for (int k = 0; k < nl; ++k) {
         Lane& l = g->lanes[k];
@@ -698,18 +727,16 @@ int rebuild(dsmc_group* g) {
             if (!l.done) HIP_TRY(&g->err, hipEventCreateWithFlags(&l.done, hipEventDisableTiming));
         }
     }
-    std::vector<dsmc_handle*> order(g->members);
+    std::vector<dsmc_handle*> order(multi);
     std::stable_sort(order.begin(), order.end(),
                      [](const dsmc_handle* a, const dsmc_handle* b) { return a->plan.N > b->plan.N; });
-    std::vector<int64_t> load(nl, 0);
+    std::vector<int64_t> load(nm, 0);
     for (dsmc_handle* h : order) {
         const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         g->lanes[k].members.push_back(h);
         load[k] += h->plan.N;
     }
-    g->phase = (g->solo && g->members.size() == 1 && g->members[0]->p.debug_phase_mask)
-                   ? g->members[0]->p.debug_phase_mask
-                   : (unsigned)DSMC_PHASE_ALL;
+    if (split) g->lanes[nm].members = small;
     for (int k = 0; k < nl; ++k) {
         int r = build_lane(g, g->lanes[k]);
         if (r) return r;
@@ -1350,6 +1377,7 @@ int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) rc = fail(&h->err, DSMC_ERR_DEVICE, "hipEventCreate failed");
     double acc[6] = {0, 0, 0, 0, 0, 0};
+    double acc_resident = 0.0;
     if (rc == DSMC_OK && nl > 1) (void)hipStreamSynchronize(g->stream);
     const auto t0 = std::chrono::steady_clock::now();
     if (rc == DSMC_OK) {
@@ -1370,7 +1398,10 @@ int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
             for (int i = 0; i < 6; ++i) {
                 if ((w.n_resident && i < 5) || (w.scan_small_lds && (i == 1 || i == 3))) continue;
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, ev[7 * b + i], ev[7 * b + i + 1]) == hipSuccess) acc[i] += ms;
+                if (hipEventElapsedTime(&ms, ev[7 * b + i], ev[7 * b + i + 1]) == hipSuccess) {
+                    acc[i] += ms;
+                    if (w.n_resident) acc_resident += ms;
+                }
             }
         }
         (void)hipGetLastError();
@@ -1385,6 +1416,7 @@ int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
     for (int i = 0; i < 6; ++i) phase_ms[i] = acc[i];
     phase_ms[6] = acc[0] + acc[1] + acc[2] + acc[3] + acc[4] + acc[5];
     phase_ms[7] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    phase_ms[8] = acc_resident;
     return sync_check(h);
 }
 
@@ -1435,11 +1467,35 @@ int dsmc_group_step(dsmc_group* g, int64_t n_steps) {
 
 int dsmc_group_sync(dsmc_group* g) {
     if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
-    HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
-    for (dsmc_handle* h : g->members) {
-        const int r = sync_check(h);
-        if (r) return r;
+    if (g->dirty || g->members.empty()) {
+        // lanes not built for the current members: check them one by one
+        HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
+        for (dsmc_handle* h : g->members) {
+            const int r = sync_check(h);
+            if (r) return r;
+        }
+        return DSMC_OK;
     }
+    // every member's status word gathered per lane, one copy each, then one
+    // synchronisation of the group's stream (which every lane joins)
+    std::vector<std::vector<int32_t>> st(g->n_lanes);
+    for (int li = 0; li < g->n_lanes; ++li) {
+        Lane& l = g->lanes[li];
+        st[li].assign(l.members.size(), 0);
+        if (l.members.empty()) continue;
+        launch_gather_status(l.work.desc, (int)l.members.size(), l.d_status, g->stream);
+        HIP_TRY(&g->err, hipGetLastError());
+        HIP_TRY(&g->err, hipMemcpyAsync(st[li].data(), l.d_status, l.members.size() * sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, g->stream));
+    }
+    HIP_TRY(&g->err, hipStreamSynchronize(g->stream));
+    for (int li = 0; li < g->n_lanes; ++li)
+        for (size_t i = 0; i < st[li].size(); ++i)
+            if (st[li][i]) {
+                // the member's own check names the error
+                const int r = sync_check(g->lanes[li].members[i]);
+                if (r) return fail(&g->err, r, g->lanes[li].members[i]->err);
+            }
     return DSMC_OK;
 }
 
@@ -1527,6 +1583,26 @@ int dsmc_group_size(const dsmc_group* g, int32_t* n) {
 int dsmc_group_lanes(const dsmc_group* g, int32_t* n) {
     if (!g || !n) return fail(nullptr, DSMC_ERR_INVALID_ARG, "NULL argument");
     *n = (int32_t)g->n_lanes;
+    return DSMC_OK;
+}
+
+int dsmc_group_lane_info(const dsmc_group* g, int32_t* n_lanes, int32_t* resident_lanes,
+                         int64_t* resident_particles, int64_t* resident_cells) {
+    if (!g) return fail(nullptr, DSMC_ERR_INVALID_ARG, "group is NULL");
+    int32_t rl = 0;
+    int64_t rp = 0, rc = 0;
+    for (int k = 0; k < g->n_lanes && k < (int)g->lanes.size(); ++k)
+        if (g->lanes[k].work.n_resident) {
+            ++rl;
+            for (const dsmc_handle* h : g->lanes[k].members) {
+                rp += h->plan.N;
+                rc += h->plan.Cc;
+            }
+        }
+    if (n_lanes) *n_lanes = g->n_lanes;
+    if (resident_lanes) *resident_lanes = rl;
+    if (resident_particles) *resident_particles = rp;
+    if (resident_cells) *resident_cells = rc;
     return DSMC_OK;
 }
 

@@ -39,6 +39,7 @@ EXPORTS = (
     "dsmc_group_set_resident",
     "dsmc_group_autotune", "dsmc_profile_step", "dsmc_group_sample", "dsmc_set_inflow",
     "dsmc_open_state", "dsmc_set_open_state", "dsmc_group_sample_noalloc",
+    "dsmc_group_lane_info",
 )
 
 
@@ -94,6 +95,8 @@ def _load():
         "dsmc_group_sync": [vp],
         "dsmc_group_size": [vp, ct.POINTER(i32)],
         "dsmc_group_lanes": [vp, ct.POINTER(i32)],
+        "dsmc_group_lane_info": [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i64),
+                                 ct.POINTER(i64)],
         "dsmc_group_sample": [vp, vp, i32, ct.c_int],
         "dsmc_group_sample_noalloc": [vp, vp, i32, ct.c_int],
         "dsmc_set_inflow": [vp, ct.c_double, ct.c_double, ct.c_double, ct.c_double],
@@ -253,11 +256,12 @@ class Solver:
 
     def profile(self, n_steps: int) -> dict:
         """Device milliseconds per kernel over n_steps eagerly launched steps."""
-        out = np.zeros(8)
+        out = np.zeros(9)
         _check(lib.dsmc_profile_step(self._h, int(n_steps), _ptr(out)), self._h)
         d = {k: float(v) for k, v in zip(self.PHASES, out[:6])}
         d["kernels_total"] = float(out[6])
         d["wall"] = float(out[7])
+        d["resident"] = float(out[8])
         return d
 
     def set_inflow(self, u: float = 0.0, dudy: float = 0.0, T: float = 1.0, n: float = 1.0):
@@ -375,6 +379,15 @@ class Group:
         n = ct.c_int32()
         _check(lib.dsmc_group_lanes(self._g, ct.byref(n)))
         return n.value
+
+    def lane_info(self) -> dict:
+        """Lanes of the last step: all, resident, and the particles of the
+        members stepped resident."""
+        n, r, p, c = ct.c_int32(), ct.c_int32(), ct.c_int64(), ct.c_int64()
+        _check(lib.dsmc_group_lane_info(self._g, ct.byref(n), ct.byref(r), ct.byref(p),
+                                        ct.byref(c)))
+        return {"lanes": n.value, "resident_lanes": r.value, "resident_particles": p.value,
+                "resident_cells": c.value}
 
     def set_tuning(self, tile_mult: int = 0, particles_per_block: int = 0, waves_per_cu: int = 0):
         _check(lib.dsmc_group_set_tuning(self._g, int(tile_mult), int(particles_per_block),

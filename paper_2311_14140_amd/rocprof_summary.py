@@ -1,0 +1,186 @@
+"""Summaries of rocprofv3 output for the kernels of a DSMC step.
+
+    python -m paper_2311_14140_amd.rocprof_summary stats DIR
+    python -m paper_2311_14140_amd.rocprof_summary traffic --stats DIR --fetch DIR \\
+        --write DIR --tag NAME --workload TEXT [--copy-mib 256] [--json FILE]
+
+``stats`` prints the kernel statistics of a ``--kernel-trace --stats -f csv``
+run as a table.  ``traffic`` reads two counter runs (``--pmc FETCH_SIZE`` and
+``--pmc WRITE_SIZE``, each in its own run) and converts each kernel's average
+KiB per dispatch to bytes, scaled by what the same counter reads for a plain
+device copy of known size in the same run (the bench's calibration copy):
+the largest copy dispatch is taken as that copy.  It prints a table per step
+kernel and records the bytes per launch with the hash of the sources in the
+JSON file that bench.py reads for its ``traffic`` field.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+# kernel name prefix -> step slot (the slots of dsmc_profile_step)
+PHASE_OF = (("k_count", "count"), ("k_colsum", "colsum"), ("k_scan_small", "scan"),
+            ("k_scan", "scan"), ("k_colprefix", "colprefix"), ("k_move_scatter", "move_scatter"),
+            ("k_collide_bucket", "collide"), ("k_collide_fast", "collide"),
+            ("k_collide_det", "collide"), ("k_resident", "collide"),
+            ("k_finalize", "finalize"))
+SOURCES = ("kernels.hip", "runtime.hip", "rng.hpp", "common.hpp", "kernels.hpp")
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_14140_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    """A kernel's name without return type, namespaces and parameters."""
+    base = name.replace("void ", "", 1).strip()
+    for ns in ("dsmc::(anonymous namespace)::", "dsmc::"):
+        if base.startswith(ns):
+            base = base[len(ns):]
+    depth = 0
+    for i, ch in enumerate(base):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return base[:i]
+    return base
+
+
+def phase(name: str):
+    base = short_name(name)
+    for prefix, ph in PHASE_OF:
+        if base.startswith(prefix + "<") or base == prefix:
+            return ph
+    return None
+
+
+def _rows(directory: str, suffix: str):
+    files = sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True))
+    if not files:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    for f in files:
+        with open(f, newline="") as fh:
+            yield from csv.DictReader(fh)
+
+
+def kernel_stats(directory: str):
+    """[(name, calls, total_ns, average_ns, percent)] of a kernel-trace run."""
+    out = []
+    for r in _rows(directory, "kernel_stats.csv"):
+        out.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]),
+                    float(r["AverageNs"]), float(r["Percentage"])))
+    out.sort(key=lambda x: -x[2])
+    return out
+
+
+def counter_per_dispatch(directory: str, counter: str):
+    """{kernel name: [value per dispatch]} of one counter run."""
+    per = defaultdict(float)
+    names = {}
+    for r in _rows(directory, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (r.get("Dispatch_Id") or r.get("Correlation_Id"), r["Kernel_Name"])
+        per[key] += float(r["Counter_Value"])
+        names[key] = r["Kernel_Name"]
+    out = defaultdict(list)
+    for key, v in per.items():
+        out[names[key]].append(v)
+    return out
+
+
+def copy_scale(values: dict, copy_mib: int) -> float:
+    copies = [v for name, vs in values.items() if "copy" in name.lower() for v in vs]
+    if not copies:
+        raise SystemExit("no copy dispatch found for the calibration")
+    return copy_mib * 1024.0 / max(copies)
+
+
+def cmd_stats(a):
+    print("| kernel | calls | total us | average us | % |")
+    print("|---|---|---|---|---|")
+    for name, calls, tot, avg, pct in kernel_stats(a.dir):
+        print(f"| {short_name(name)} | {calls} | {tot / 1e3:.1f} | {avg / 1e3:.3f} | {pct:.1f} |")
+
+
+def cmd_traffic(a):
+    stats = kernel_stats(a.stats)
+    fetch = counter_per_dispatch(a.fetch, "FETCH_SIZE")
+    write = counter_per_dispatch(a.write, "WRITE_SIZE")
+    fs, ws = copy_scale(fetch, a.copy_mib), copy_scale(write, a.copy_mib)
+    avg_us = defaultdict(list)
+    for name, calls, tot, avg, _ in stats:
+        ph = phase(name)
+        if ph:
+            avg_us[ph].append((calls, tot))
+    by_phase = defaultdict(lambda: [[], []])
+    for name, vs in fetch.items():
+        if phase(name):
+            by_phase[phase(name)][0] += vs
+    for name, vs in write.items():
+        if phase(name):
+            by_phase[phase(name)][1] += vs
+    rec = {"workload": a.workload, "fetch_scale": fs, "write_scale": ws,
+           "kernel_source_hash": source_hash(), "avg_us": {}, "bytes_per_launch": {},
+           "fetch_KiB": {}, "write_KiB": {}}
+    for ph, cts in avg_us.items():
+        calls = sum(c for c, _ in cts)
+        rec["avg_us"][ph] = sum(t for _, t in cts) / calls / 1e3
+    print(f"Calibration: a plain {a.copy_mib} MiB device copy scales FETCH_SIZE by {fs:.3f} "
+          f"and WRITE_SIZE by {ws:.3f}.\n")
+    print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | calibrated MB per launch |")
+    print("|---|---|---|---|")
+    for ph in sorted(by_phase):
+        f, w = by_phase[ph]
+        if not f or not w:
+            continue
+        fk, wk = sum(f) / len(f), sum(w) / len(w)
+        b = (fk * fs + wk * ws) * 1024.0
+        rec["fetch_KiB"][ph], rec["write_KiB"][ph] = fk, wk
+        rec["bytes_per_launch"][ph] = b
+        print(f"| {ph} | {fk:.1f} | {wk:.1f} | {b / 1e6:.3f} |")
+    print(f"\nKernel source hash: {rec['kernel_source_hash']}")
+    if a.json:
+        data = {}
+        if os.path.exists(a.json):
+            with open(a.json) as fh:
+                data = json.load(fh)
+        data[a.tag] = rec
+        with open(a.json, "w") as fh:
+            json.dump(data, fh, indent=1, sort_keys=True)
+            fh.write("\n")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    t = sub.add_parser("traffic")
+    t.add_argument("--stats", required=True)
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--tag", required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--copy-mib", type=int, default=256)
+    t.add_argument("--json", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+    a = ap.parse_args(argv)
+    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -137,11 +137,13 @@ def _cell_bins(profile, bins):
 def test_fp32_batched_mix_every_instance_matches_oracle(D):
     """Every instance of the 256-instance batched mix (Kn 0.05..10, 50..2000
     cells, 20..200 per cell), FP32 and run as one group per replica, against
-    the oracle's replicas of the same instance on the same short schedule.
-    Profiles are compared as 16 cell-bin averages per instance; the mass flow
-    of each instance by its own Welch statistic."""
+    the oracle's replicas of the same instance on the same schedule (100
+    transient + 1000 sampling steps).  Profiles are compared as 16 cell-bin
+    averages per instance; the mass flow of each instance by its own Welch
+    statistic, and within 0.5% wherever three standard errors of the
+    difference are below 0.5% of the flow."""
     files = sorted(f for f in os.listdir(os.path.join(HERE, "golden"))
-                   if f.startswith("oracle_cfg3_mix_r") and f.endswith(".npz"))
+                   if f.startswith("oracle_cfg3_mix_s1000_r") and f.endswith(".npz"))
     if not files:
         pytest.skip("oracle reference for the batched mix not generated")
     parts = [np.load(os.path.join(HERE, "golden", f)) for f in files]
@@ -182,6 +184,24 @@ def test_fp32_batched_mix_every_instance_matches_oracle(D):
     b = {q: d[q].transpose(1, 0, 2).reshape(R, -1) for q in QUANT}
     assert_profiles_agree(a, b)
     assert_profiles_agree({"Q": Q.T}, {"Q": d["mass_flow"].T}, quantities=("Q",))
+    # the 0.5% mass-flow criterion.  Over 1000 sampled steps one instance's
+    # flow is resolved to a few percent at best, so the criterion is applied
+    # per instance only where three standard errors reach 0.5%, and to the
+    # instances' relative differences pooled with inverse-variance weights,
+    # which the 256 instances resolve well below 0.5%
+    qg, qo = Q.mean(1), d["mass_flow"].mean(1)
+    se = np.sqrt(Q.var(1, ddof=1) / R + d["mass_flow"].var(1, ddof=1) / R)
+    rel = (qg - qo) / np.abs(qo)
+    srel = se / np.abs(qo)
+    resolved = 3.0 * srel <= 0.005
+    assert np.all(np.abs(rel[resolved]) <= 0.005), np.flatnonzero(resolved & (np.abs(rel) > 0.005))
+    w = 1.0 / srel ** 2
+    pooled = float(np.sum(w * rel) / np.sum(w))
+    pooled_se = float(1.0 / math.sqrt(np.sum(w)))
+    print(f"mass flow: {resolved.sum()} of {len(inst)} instances resolved to 0.5% at 3 SE; pooled "
+          f"relative difference {100 * pooled:+.4f}% (3 SE = {300 * pooled_se:.4f}%)")
+    assert 3.0 * pooled_se <= 0.005, pooled_se
+    assert abs(pooled) <= 0.005, pooled
 
 
 def test_fast_collision_rate(D):
@@ -603,3 +623,38 @@ def test_moment_sums_match_the_particle_state(D, prec_name, ppc):
         want = np.bincount(cell, weights=t, minlength=raw.shape[0])
         scale = np.bincount(cell, weights=np.abs(t), minlength=raw.shape[0])
         assert np.all(np.abs(raw[:, k] - want) <= 1e-12 * scale + 1e-300), k
+
+
+@pytest.mark.parametrize("prec_name", ["DSMC_FP32_FAST", "DSMC_FP64_FAST"])
+def test_large_tiles_equal_held_tiles(D, prec_name):
+    """Instances with full collision cells sort by cell.  A tile larger than
+    the move-scatter holds in registers is counted from the position-only
+    flight first and then moved and placed round by round; tiles eight times
+    larger than the automatic ones (held, and at FP64 staged) take that path,
+    at low Kn and at high Kn, where particles cross many cells per step.
+    Every state, cell table and window sum equals the automatic tiles' bit
+    for bit."""
+    prec = getattr(D, prec_name)
+    ps = [Params(kn=0.05, body_force=0.01, n_cells=400, particles_per_cell=300, seed=31,
+                 n_transient=3, precision=prec),
+          Params(kn=2.0, body_force=0.02, n_cells=300, particles_per_cell=280, seed=32,
+                 n_transient=3, precision=prec)]
+    out = []
+    for tile_mult in (1, 8):
+        g = D.Group()
+        sols = [D.Solver(p) for p in ps]
+        for s in sols:
+            g.add(s)
+        g.set_tuning(tile_mult, 0, 0)
+        g.step(13)
+        g.sync()
+        out.append([(s.get_state(), s.get_cells(), s.sample(raw=True)["raw"]) for s in sols])
+        g.close()
+        for s in sols:
+            s.close()
+    for (sa, ca, ra), (sb, cb, rb) in zip(out[0], out[1]):
+        for a, b in zip(sa, sb):
+            assert np.array_equal(np.asarray(a), np.asarray(b))
+        for a, b in zip(ca, cb):
+            assert np.array_equal(a, b)
+        assert np.array_equal(ra, rb)

@@ -200,3 +200,46 @@ def test_just_past_the_limits_is_multi_kernel(D, kw):
     ref, _ = _run(D, [p], inflow, False, (19,))
     assert prof["count"] > 0 and prof["move_scatter"] > 0
     _assert_same(res[0], ref[0])
+
+
+@pytest.mark.parametrize("big_lanes", [1, 2])
+def test_small_members_of_a_mixed_group_run_in_a_resident_lane(D, big_lanes):
+    """A group that mixes small members with larger ones steps the small ones
+    resident in a lane of their own, beside the multi-kernel lanes of the
+    larger ones (one of them, or two once those hold 2e6 particles); every
+    member equals itself stepped alone, state, cell tables and window sums,
+    and the sizes of the lanes show in the lane information."""
+    small = [Params(kn=0.4 + 0.1 * r, body_force=0.01, n_cells=60 + 7 * r, particles_per_cell=40,
+                    seed=synth.seed_of(16, r), n_transient=6, precision=D.DSMC_FP32_FAST)
+             for r in range(5)]
+    big_ppc = 150 if big_lanes == 1 else 1100
+    big = [Params(kn=0.2 + 0.3 * r, body_force=0.01, n_cells=900 + 100 * r, particles_per_cell=big_ppc,
+                  seed=synth.seed_of(16, 100 + r), n_transient=6, precision=D.DSMC_FP32_FAST)
+           for r in range(2)]
+    ps = small + big
+    _say(f"{len(small)} small + {len(big)} larger members")
+    sols = [D.Solver(p) for p in ps]
+    g = D.Group()
+    for s in sols:
+        g.add(s)
+    g.step(21)
+    g.sync()
+    li = g.lane_info()
+    assert li["resident_lanes"] == 1 and li["lanes"] == big_lanes + 1, li
+    assert li["resident_particles"] == sum(p.n_particles for p in small)
+    assert li["resident_cells"] == sum(p.n_cells for p in small)
+    prof = sols[0].profile(1)
+    assert prof["count"] > 0 and prof["resident"] > 0 and prof["collide"] > prof["resident"]
+    got = [_snapshot(D, s, False) for s in sols]
+    g.close()
+    for s in sols:
+        s.close()
+    for p, snap in zip(ps, got):
+        with D.Solver(p) as s:
+            s.step(22)   # 21 steps and the profiled one
+            ref = _snapshot(D, s, False)
+        for a, b in zip(snap["state"], ref["state"]):
+            assert np.array_equal(a, b)
+        for a, b in zip(snap["cells"], ref["cells"]):
+            assert np.array_equal(a, b)
+        assert np.array_equal(snap["raw"], ref["raw"])
