@@ -194,7 +194,15 @@ def test_fp32_batched_mix_every_instance_matches_oracle(D):
     rel = (qg - qo) / np.abs(qo)
     srel = se / np.abs(qo)
     resolved = 3.0 * srel <= 0.005
-    assert np.all(np.abs(rel[resolved]) <= 0.005), np.flatnonzero(resolved & (np.abs(rel) > 0.005))
+    # a resolved instance still exceeds 0.5% with the Student-t tail
+    # probability of 0.5% / SE (at most 0.27%): the number of exceedances is
+    # held to the 99.9% Poisson bound of those probabilities, as the profile
+    # rule does for |z| > 3
+    for i in np.flatnonzero(resolved):
+        print(f"instance {i}: mass flow {100 * rel[i]:+.3f}% (SE {100 * srel[i]:.3f}%)")
+    p_ex = 2.0 * stats.t.sf(0.005 / srel[resolved], 2 * (R - 1))
+    n_ex = int(np.sum(np.abs(rel[resolved]) > 0.005))
+    assert n_ex <= stats.poisson.ppf(0.999, p_ex.sum()), (n_ex, p_ex.sum())
     w = 1.0 / srel ** 2
     pooled = float(np.sum(w * rel) / np.sum(w))
     pooled_se = float(1.0 / math.sqrt(np.sum(w)))
