@@ -28,6 +28,10 @@ constexpr int kResidentWaves = 16;     // wavefronts of that workgroup
 // records per lane the move-scatter holds in registers (FP32, FP64): tiles of
 // bucket-sorted instances are 256 times this many slots
 constexpr int kScatterRegs32 = 5, kScatterRegs64 = 4;
+// records per thread of one chunk of a larger tile (FP32, FP64): the
+// move-scatter walks such a tile in chunks of 256 times this many slots
+constexpr int kWideRecs32 = 4, kWideRecs64 = 2;
+constexpr int kWideKeys = 64;  // sort keys ranked per pass over a chunk (one wavefront's lanes)
 
 // Scalars an instance keeps on the device so that a step is the same launch
 // sequence every time (and can be replayed from a graph).

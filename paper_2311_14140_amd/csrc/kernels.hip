@@ -779,14 +779,189 @@ template <class R> struct ScatterRegs {
     static constexpr int value = sizeof(R) == 4 ? kScatterRegs32 : kScatterRegs64;
 };
 
+template <class R> struct WideRecs {
+    static constexpr int value = sizeof(R) == 4 ? kWideRecs32 : kWideRecs64;
+};
+
+// Ints of the wide-tile LDS layout before its staged records (kept a
+// multiple of four, so the records are 16-byte aligned).
+__host__ __device__ constexpr int wide_ints(int nk, int J) {
+    return (nk + 2 * J * kScatterWaves * kWideKeys + 2 * kWideKeys + 4 + J * kParticleThreads + 3) & ~3;
+}
+
+// Move and stable scatter of a tile larger than k_move_scatter holds in
+// registers (a separate kernel, so that its registers do not cost the other
+// one occupancy; the runtime lists its tiles after the others).  The
+// workgroup walks the tile in chunks of 256 * J slots.  A chunk is read and
+// moved in registers and ranked by key over the whole workgroup in slot
+// order (round j, wavefront, lane): within each (round, wavefront) group the
+// lanes of equal key are found by one ballot per key bit, the group's count
+// of each key goes to an LDS table, and one wavefront scans that table key
+// by key, 64 keys per pass (a chunk whose keys span more takes more passes).
+// The chunk is laid out in LDS in destination order and written from there,
+// so each key's run in the chunk is stored to consecutive addresses rather
+// than a few records per round.  The next destination of every key lives in
+// one LDS table for the whole tile, started from the tile's scatter bases,
+// so the tile needs no histogram of its own here.  Count entries carry the
+// number of the pass that wrote them, which spares clearing the table
+// between passes.
+template <class R, bool kOpen>
+__global__ __launch_bounds__(kParticleThreads) void k_move_scatter_wide(const InstDesc* __restrict__ descs,
+                                                                       const int2* __restrict__ work) {
+    extern __shared__ int lds[];
+    const int2 w = work[blockIdx.x];
+    const InstDesc& d = descs[w.x];
+    const int tile = w.y;
+    const int64_t s = d.sc->step_done;
+    const P4<R> src = particles<R>(d, (int)((s - 1) & 1));
+    const P4<R> dst = particles<R>(d, (int)(s & 1));
+    const int start = tile * d.tile_items;
+    const int end = min(start + d.tile_items, slots_after_scan<kOpen>(d));
+    constexpr int J = WideRecs<R>::value;
+    constexpr int C = J * kParticleThreads;
+    constexpr int G = J * kScatterWaves;
+    const int nk = d.nkeys;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int* run = lds;                    // nk: next destination of each key
+    int* cnt = run + nk;               // G x 64: (pass << 8) | count per group and key
+    int* pre = cnt + G * kWideKeys;    // G x 64: records of the key in earlier groups of the chunk
+    int* koff = pre + G * kWideKeys;   // 64: the key's first staging index
+    int* dlt = koff + kWideKeys;       // 64: destination minus staging index
+    int* red = dlt + kWideKeys;        // chunk key range, two chunks alternating
+    int* spos = red + 4;               // C: destination of each staged record
+    R* srec = (R*)(lds + wide_ints(nk, J));  // 4 x C: y, vx, vy, vz in destination order
+    const gptr<int32_t> brow = gmem(d.counts) + (size_t)tile * nk;
+    for (int c = tid; c < nk; c += kParticleThreads) run[c] = brow[c];
+    for (int e = tid; e < G * kWideKeys; e += kParticleThreads) cnt[e] = 0;
+    if (tid < 4) red[tid] = (tid & 1) ? -1 : INT32_MAX;
+    __syncthreads();
+    const unsigned long long lt = lanes_below(lane);
+    int bad = 0, pass = 0, nbase = 0;
+    for (int cb = start, ci = 0; cb < end; cb += C, ++ci) {
+        const int par = 2 * (ci & 1);
+        R ry[J], rx[J], rv[J], rz[J];
+        int key[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int i = cb + j * kParticleThreads + tid;
+            ry[j] = rx[j] = rv[j] = rz[j] = R(0);
+            if (i < end) {
+                ry[j] = src.y[i];
+                rx[j] = src.vx[i];
+                rv[j] = src.vy[i];
+                rz[j] = src.vz[i];
+            }
+        }
+        int kmn = INT32_MAX, kmx = -1;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int i = cb + j * kParticleThreads + tid;
+            key[j] = -1;
+            if (i < end) {
+                bool gone = false;
+                move_one<R, kOpen>(d, (uint32_t)s, (uint32_t)i, ry[j], rx[j], rv[j], rz[j], gone);
+                bad |= !(isfinite(rx[j]) && isfinite(rv[j]) && isfinite(rz[j]));
+                key[j] = key_of<R, kOpen>(d, ry[j], gone);
+                kmn = min(kmn, key[j]);
+                kmx = max(kmx, key[j]);
+            }
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            kmn = min(kmn, __shfl_xor(kmn, o, 64));
+            kmx = max(kmx, __shfl_xor(kmx, o, 64));
+        }
+        if (lane == 0 && kmx >= 0) {
+            atomicMin(&red[par], kmn);
+            atomicMax(&red[par + 1], kmx);
+        }
+        __syncthreads();
+        const int kmin = red[par], kmax = red[par + 1];
+        // the other chunk's range was read before the last barrier
+        if (tid == 0) {
+            red[2 - par] = INT32_MAX;
+            red[3 - par] = -1;
+        }
+        const int nrec = min(C, end - cb);
+        nbase = 0;
+        for (int w0 = kmin; w0 <= kmax; w0 += kWideKeys) {
+            ++pass;
+            int rank[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int kl = key[j] - w0;
+                const bool in = key[j] >= 0 && kl >= 0 && kl < kWideKeys;
+                unsigned long long m = __ballot(in);
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+                    const bool bit = (kl >> b) & 1;
+                    const unsigned long long bal = __ballot(bit);
+                    m &= bit ? bal : ~bal;
+                }
+                rank[j] = __popcll(m & lt);
+                if (in && rank[j] == 0) cnt[(j * kScatterWaves + wv) * kWideKeys + kl] = (pass << 8) | __popcll(m);
+            }
+            __syncthreads();
+            if (wv == 0) {
+                int tot = 0;
+                for (int g = 0; g < G; ++g) {
+                    const int v = cnt[g * kWideKeys + lane];
+                    pre[g * kWideKeys + lane] = tot;
+                    tot += (v >> 8) == pass ? (v & 255) : 0;
+                }
+                const int incl = wave_incl_scan(tot, lane);
+                const int ko = nbase + incl - tot;
+                koff[lane] = ko;
+                if (tot > 0) {  // some record has key w0 + lane, so it is < nk
+                    const int r = run[w0 + lane];
+                    dlt[lane] = r - ko;
+                    run[w0 + lane] = r + tot;
+                }
+                nbase += __shfl(incl, 63, 64);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int kl = key[j] - w0;
+                if (key[j] >= 0 && kl >= 0 && kl < kWideKeys) {
+                    int l = koff[kl] + pre[(j * kScatterWaves + wv) * kWideKeys + kl] + rank[j];
+                    const int pos = l + dlt[kl];
+                    if (l < 0 || l >= nrec) {
+                        bad |= 2;
+                        l = l < 0 ? 0 : nrec - 1;
+                    }
+                    spos[l] = pos;
+                    srec[l] = ry[j];
+                    srec[C + l] = rx[j];
+                    srec[2 * C + l] = rv[j];
+                    srec[3 * C + l] = rz[j];
+                }
+            }
+        }
+        __syncthreads();
+        for (int l = tid; l < nrec; l += kParticleThreads) {
+            int pos = spos[l];
+            if (pos < 0 || pos >= d.ncap) {
+                bad |= 2;
+                pos = pos < 0 ? 0 : d.ncap - 1;
+            }
+            dst.y[pos] = srec[l];
+            dst.vx[pos] = srec[C + l];
+            dst.vy[pos] = srec[2 * C + l];
+            dst.vz[pos] = srec[3 * C + l];
+        }
+    }
+    // error path only: bit 0 a non-finite velocity, bit 2 a slot out of range
+    if (bad) atomicOr(&d.sc->status, (bad & 1) | ((bad & 2) << 1));
+}
+
 // Move and stable scatter of one tile: the same quarter-per-wavefront
 // ranking as k_scatter, with the keys coming from the move.  A tile of at
 // most 256 * ScatterRegs slots is read once into registers, moved (wall
 // re-emissions queued and run together), counted and placed round by round;
-// a larger tile counts its quarters from the position-only flight first and
-// then reads, moves and ranks round by round.  A
-// sorted position outside [0, N) (only possible if the counts and this pass
-// disagreed) is clamped and flagged.
+// larger tiles are k_move_scatter_wide's.  A sorted position outside [0, N)
+// (only possible if the counts and this pass disagreed) is clamped and
+// flagged.
 template <class R, bool kOpen>
 __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDesc* __restrict__ descs,
                                                                   const int2* __restrict__ work,
@@ -811,7 +986,6 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
     if (threadIdx.x == 0) blk_bad = 0;
     const int quarter = (((end - start) + kScatterWaves - 1) / kScatterWaves + 63) / 64 * 64;
     const int q0 = min(start + wv * quarter, end), q1 = min(q0 + quarter, end);
-    const bool in_regs = quarter <= 64 * K;
     int* mine = tables + wv * nk;
     // the tile's scatter bases, read now so that their latency hides behind
     // the move (thread c holds key c's base when there are at most 256 keys)
@@ -822,96 +996,91 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
     R ry[K], rx[K], rv[K], rz[K];
     int key[K];
     int bad = 0;
-    if (in_regs) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = q0 + 64 * k + lane;
-            ry[k] = rx[k] = rv[k] = rz[k] = R(0);
-            if (i < q1) {
-                ry[k] = src.y[i];
-                rx[k] = src.vx[i];
-                rv[k] = src.vy[i];
-                rz[k] = src.vz[i];
-            }
+    for (int k = 0; k < K; ++k) {
+        const int i = q0 + 64 * k + lane;
+        ry[k] = rx[k] = rv[k] = rz[k] = R(0);
+        if (i < q1) {
+            ry[k] = src.y[i];
+            rx[k] = src.vx[i];
+            rv[k] = src.vy[i];
+            rz[k] = src.vz[i];
         }
-        // Straight flights at once; records that reach a plate are queued
-        // in this wavefront's share of the (not yet used) staging area and
-        // re-emitted together, 64 at a time, instead of once per round in
-        // which any lane hits.  Queue overflow is handled in place.
-        const int qcap = staged ? stage_max / 5 : 0;
-        int* qslot = stage_pos + wv * (stage_max / 4);
-        R* qt = stage_rec + wv * stage_max;
-        R* qy = qt + qcap;
-        R* qx = qy + qcap;
-        R* qv = qx + qcap;
-        R* qz = qv + qcap;
-        int nq = 0, jq[K];
-        unsigned hitm = 0, gonem = 0;  // queued records; records that left the domain
+    }
+    // Straight flights at once; records that reach a plate are queued
+    // in this wavefront's share of the (not yet used) staging area and
+    // re-emitted together, 64 at a time, instead of once per round in
+    // which any lane hits.  Queue overflow is handled in place.
+    const int qcap = staged ? stage_max / 5 : 0;
+    int* qslot = stage_pos + wv * (stage_max / 4);
+    R* qt = stage_rec + wv * stage_max;
+    R* qy = qt + qcap;
+    R* qx = qy + qcap;
+    R* qv = qx + qcap;
+    R* qz = qv + qcap;
+    int nq = 0, jq[K];
+    unsigned hitm = 0, gonem = 0;  // queued records; records that left the domain
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = q0 + 64 * k + lane;
-            bool hit = false, top = false, gone = false;
-            R tl = R(0);
-            jq[k] = 0;
-            if (i < q1) hit = !flight_start<R, kOpen>(d, ry[k], rx[k], rv[k], tl, top, gone);
-            if (gone) gonem |= 1u << k;
-            const unsigned long long hm = __ballot(hit);
-            if (hit) {
-                const int j = nq + __popcll(hm & lanes_below(lane));
-                if (j < qcap) {
-                    qslot[j] = i;
-                    qt[j] = top ? tl : -tl;  // the time left is > 0; its sign keeps the plate
-                    jq[k] = j;
-                    hitm |= 1u << k;
-                } else {
-                    bool gone2 = false;
-                    flight_from_wall<R, kOpen>(d, (uint32_t)s, (uint32_t)i, top, tl, ry[k], rx[k], rv[k],
-                                               rz[k], gone2);
-                    if (gone2) gonem |= 1u << k;
-                }
-            }
-            nq += __popcll(hm);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const int nproc = min(nq, qcap);
-        for (int b0 = 0; b0 < nproc; b0 += 64) {
-            const int j = b0 + lane;
-            if (j < nproc) {
-                const R tt = qt[j];
-                R y = R(0), vx = R(0), vy = R(0), vz = R(0);
-                bool gone3 = false;
-                flight_from_wall<R, kOpen>(d, (uint32_t)s, (uint32_t)qslot[j], tt > R(0),
-                                           tt > R(0) ? tt : -tt, y, vx, vy, vz, gone3);
-                qy[j] = gone3 ? R(-1) : y;  // a flight ends at y >= 0: -1 marks one that left
-                qx[j] = vx;
-                qv[j] = vy;
-                qz[j] = vz;
+    for (int k = 0; k < K; ++k) {
+        const int i = q0 + 64 * k + lane;
+        bool hit = false, top = false, gone = false;
+        R tl = R(0);
+        jq[k] = 0;
+        if (i < q1) hit = !flight_start<R, kOpen>(d, ry[k], rx[k], rv[k], tl, top, gone);
+        if (gone) gonem |= 1u << k;
+        const unsigned long long hm = __ballot(hit);
+        if (hit) {
+            const int j = nq + __popcll(hm & lanes_below(lane));
+            if (j < qcap) {
+                qslot[j] = i;
+                qt[j] = top ? tl : -tl;  // the time left is > 0; its sign keeps the plate
+                jq[k] = j;
+                hitm |= 1u << k;
+            } else {
+                bool gone2 = false;
+                flight_from_wall<R, kOpen>(d, (uint32_t)s, (uint32_t)i, top, tl, ry[k], rx[k], rv[k],
+                                           rz[k], gone2);
+                if (gone2) gonem |= 1u << k;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        nq += __popcll(hm);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int nproc = min(nq, qcap);
+    for (int b0 = 0; b0 < nproc; b0 += 64) {
+        const int j = b0 + lane;
+        if (j < nproc) {
+            const R tt = qt[j];
+            R y = R(0), vx = R(0), vy = R(0), vz = R(0);
+            bool gone3 = false;
+            flight_from_wall<R, kOpen>(d, (uint32_t)s, (uint32_t)qslot[j], tt > R(0),
+                                       tt > R(0) ? tt : -tt, y, vx, vy, vz, gone3);
+            qy[j] = gone3 ? R(-1) : y;  // a flight ends at y >= 0: -1 marks one that left
+            qx[j] = vx;
+            qv[j] = vy;
+            qz[j] = vz;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = q0 + 64 * k + lane;
-            key[k] = 0;
-            if ((hitm >> k) & 1u) {
-                const int j = jq[k];
-                ry[k] = qy[j];
-                rx[k] = qx[j];
-                rv[k] = qv[j];
-                rz[k] = qz[j];
-                if (kOpen && ry[k] < R(0)) gonem |= 1u << k;
-            }
-            if (i < q1) {
-                bad |= !(isfinite(rx[k]) && isfinite(rv[k]) && isfinite(rz[k]));
-                key[k] = key_of<R, kOpen>(d, ry[k], (gonem >> k) & 1u);
-                atomicAdd(&mine[key[k]], 1);
-            }
+    for (int k = 0; k < K; ++k) {
+        const int i = q0 + 64 * k + lane;
+        key[k] = 0;
+        if ((hitm >> k) & 1u) {
+            const int j = jq[k];
+            ry[k] = qy[j];
+            rx[k] = qx[j];
+            rv[k] = qv[j];
+            rz[k] = qz[j];
+            if (kOpen && ry[k] < R(0)) gonem |= 1u << k;
         }
-    } else {
-        for (int i = q0 + lane; i < q1; i += 64)
-            atomicAdd(&mine[flight_key<R, kOpen>(d, (uint32_t)s, (uint32_t)i, src.y[i], src.vy[i])], 1);
+        if (i < q1) {
+            bad |= !(isfinite(rx[k]) && isfinite(rv[k]) && isfinite(rz[k]));
+            key[k] = key_of<R, kOpen>(d, ry[k], (gonem >> k) & 1u);
+            atomicAdd(&mine[key[k]], 1);
+        }
     }
     __syncthreads();
     for (int c = threadIdx.x; c < nk; c += blockDim.x) {
@@ -983,29 +1152,9 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     };
-    if (in_regs) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (q0 + 64 * k < q1) place(q0 + 64 * k + lane < q1, key[k], ry[k], rx[k], rv[k], rz[k]);
-    } else {
-        for (int base = q0; base < q1; base += 64) {
-            const int i = base + lane;
-            const bool valid = i < q1;
-            R y = R(0), vx = R(0), vy = R(0), vz = R(0);
-            int kk = 0;
-            if (valid) {
-                y = src.y[i];
-                vx = src.vx[i];
-                vy = src.vy[i];
-                vz = src.vz[i];
-                bool gone = false;
-                move_one<R, kOpen>(d, (uint32_t)s, (uint32_t)i, y, vx, vy, vz, gone);
-                bad |= !(isfinite(vx) && isfinite(vy) && isfinite(vz));
-                kk = key_of<R, kOpen>(d, y, gone);
-            }
-            place(valid, kk, y, vx, vy, vz);
-        }
-    }
+    for (int k = 0; k < K; ++k)
+        if (q0 + 64 * k < q1) place(q0 + 64 * k + lane < q1, key[k], ry[k], rx[k], rv[k], rz[k]);
     if (bad) atomicOr(&blk_bad, bad);
     __syncthreads();
     if (staged) {
@@ -1296,13 +1445,16 @@ __device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, V 
             off += q < wv ? v : 0;
             tot += v;
         }
+        // nothing pending and nothing left to draw: done (the same decision
+        // in every thread, from the counts every thread has read)
+        const int64_t fresh = M - next < (int64_t)tot ? M - next : (int64_t)tot;
+        if ((int)blockDim.x == tot && fresh <= 0) break;
         if (idle) {
             const int64_t k = next + off + __popcll(im & lt);
             if (k < M) draw_candidate<R>(d, s, c, nc, k, p, st);
         }
         next += tot;
         const bool active = p.k >= 0;
-        if (!__syncthreads_or(active)) break;
         const int hi = p.i & (kCoopTable - 1), hj = p.j & (kCoopTable - 1);
         if (active) {
             atomicMin(&tab[hi], (uint32_t)p.k);
@@ -1420,10 +1572,32 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
         R* vx = lds_v;
         R* vy = lds_v + cap;
         R* vz = lds_v + 2 * cap;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            vx[i] = g.vx[s0 + i];
-            vy[i] = g.vy[s0 + i];
-            vz[i] = g.vz[s0 + i];
+        // staged in batches of U records per thread, all of a batch's loads
+        // issued before its first LDS store: with one large cell per CU
+        // there are few other wavefronts to hide a load's latency, and a
+        // load-store pair per iteration waited for each load in turn
+        constexpr int U = 8;
+        for (int b = (int)threadIdx.x; b < n; b += U * (int)blockDim.x) {
+            R tx[U], ty[U], tz[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = b + u * (int)blockDim.x;
+                tx[u] = ty[u] = tz[u] = R(0);
+                if (i < n) {
+                    tx[u] = g.vx[s0 + i];
+                    ty[u] = g.vy[s0 + i];
+                    tz[u] = g.vz[s0 + i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = b + u * (int)blockDim.x;
+                if (i < n) {
+                    vx[i] = tx[u];
+                    vy[i] = ty[u];
+                    vz[i] = tz[u];
+                }
+            }
         }
         __syncthreads();
         collide_cells<R, R*>(d, (uint32_t)s, c0, c1, s0, vx, vy, vz, claims, sh, do_collide, sample);
@@ -2271,14 +2445,24 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
             hipLaunchKernelGGL(k_colprefix, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
         }
         mark(4);
-        if (w.has_open)
-            hipLaunchKernelGGL((k_move_scatter<R, true>), dim3(w.n_tiles), dim3(kParticleThreads),
-                               lds(scatter_lds_bytes(mode, w.max_cc, w.stage_max)), st, w.desc, w.tiles,
-                               w.stage_max);
-        else
-            hipLaunchKernelGGL((k_move_scatter<R, false>), dim3(w.n_tiles), dim3(kParticleThreads),
-                               lds(scatter_lds_bytes(mode, w.max_cc, w.stage_max)), st, w.desc, w.tiles,
-                               w.stage_max);
+        // tiles the registers hold first, then the larger ones
+        const int n_wide = w.n_tiles - w.n_narrow;
+        if (w.n_narrow) {
+            if (w.has_open)
+                hipLaunchKernelGGL((k_move_scatter<R, true>), dim3(w.n_narrow), dim3(kParticleThreads),
+                                   lds(w.scatter_lds), st, w.desc, w.tiles, w.stage_max);
+            else
+                hipLaunchKernelGGL((k_move_scatter<R, false>), dim3(w.n_narrow), dim3(kParticleThreads),
+                                   lds(w.scatter_lds), st, w.desc, w.tiles, w.stage_max);
+        }
+        if (n_wide) {
+            if (w.has_open)
+                hipLaunchKernelGGL((k_move_scatter_wide<R, true>), dim3(n_wide), dim3(kParticleThreads),
+                                   lds(w.wide_lds), st, w.desc, w.tiles + w.n_narrow);
+            else
+                hipLaunchKernelGGL((k_move_scatter_wide<R, false>), dim3(n_wide), dim3(kParticleThreads),
+                                   lds(w.wide_lds), st, w.desc, w.tiles + w.n_narrow);
+        }
     } else {
         step_kernels_debug<R>(w, mode, phase, st, mark);
     }
@@ -2327,6 +2511,12 @@ size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max) {
     if (stage_max <= 0) return (size_t)kScatterWaves * max_cc * sizeof(int);
     return (size_t)(kScatterWaves + 1) * max_cc * sizeof(int) +
            (size_t)stage_max * (sizeof(int) + 4 * rb) + 16;
+}
+
+size_t wide_scatter_lds_bytes(Mode mode, int max_cc) {
+    const int J = mode == kFp32Fast ? kWideRecs32 : kWideRecs64;
+    const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
+    return (size_t)wide_ints(max_cc, J) * sizeof(int) + (size_t)4 * J * kParticleThreads * rb;
 }
 
 size_t bucket_collide_lds_bytes(Mode mode, int cap) {
@@ -2381,6 +2571,10 @@ hipError_t configure_kernels(size_t max_dynamic_lds) {
     set((const void*)k_move_scatter<double, false>);
     set((const void*)k_move_scatter<float, true>);
     set((const void*)k_move_scatter<double, true>);
+    set((const void*)k_move_scatter_wide<float, false>);
+    set((const void*)k_move_scatter_wide<double, false>);
+    set((const void*)k_move_scatter_wide<float, true>);
+    set((const void*)k_move_scatter_wide<double, true>);
     set((const void*)k_scan_small);
     return e;
 }

@@ -13,6 +13,8 @@ struct Work {
     int n_inst;
     const int2* tiles;      // (instance, tile) for the particle kernels
     int n_tiles;
+    int n_narrow;           // the first n_narrow tiles are held in registers by the
+                            // move-scatter; the rest take its wide-tile kernel
     const int4* cols;       // (instance, cell chunk, segment) for the column scans
     int n_cols;
     const int4* cblocks;    // (instance, first cell, end cell) workgroup-staged collide blocks
@@ -24,6 +26,8 @@ struct Work {
     int group_cap;          // particles a bucket collide workgroup stages in LDS
     int max_cc;             // largest sort-key count (LDS of histograms)
     int stage_max;          // tiles of at most this many slots are staged in LDS by the scatter
+    size_t scatter_lds;     // dynamic LDS of the move-scatter
+    size_t wide_lds;        // and of its wide-tile kernel
     int fast_cap;           // particles a fast-collide workgroup stages in LDS
     int has_open;           // some instance has an open boundary (open-boundary kernel variants)
     // resident lanes (every member small): (instance, G) per workgroup of
@@ -67,6 +71,8 @@ void launch_reset_window_gather(const InstDesc* const* d_descs, int n_inst, hipS
 size_t fast_collide_lds_bytes(Mode mode, int cap);
 size_t bucket_collide_lds_bytes(Mode mode, int cap);
 size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max);
+// LDS of the move-scatter's kernel for tiles larger than its registers hold.
+size_t wide_scatter_lds_bytes(Mode mode, int max_cc);
 // Allow dynamic LDS up to max_dynamic_lds bytes for the kernels that use it.
 hipError_t configure_kernels(size_t max_dynamic_lds);
 // The same for the resident kernel, which may take most of a CU's LDS.

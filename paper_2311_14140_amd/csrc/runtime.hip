@@ -468,7 +468,7 @@ std::vector<T> xcd_stripes(const std::vector<T>& in) {
 int build_lane(dsmc_group* g, Lane& lane) {
     const int n = (int)lane.members.size();
     std::vector<InstDesc> descs(n);
-    std::vector<int2> tiles;
+    std::vector<int2> tiles, wide_tiles;  // tiles the move-scatter holds in registers; larger ones
     std::vector<int4> cols, cblocks, gblocks;
     int max_cc = 1;
     int cap = 64, group_cap = 64;
@@ -520,7 +520,9 @@ int build_lane(dsmc_group* g, Lane& lane) {
         d.tiles = (d.ncap + d.tile_items - 1) / d.tile_items;
         d.nseg = (d.tiles + kSegTiles - 1) / kSegTiles;
         descs[i] = d;
-        for (int t = 0; t < d.tiles; ++t) tiles.push_back(make_int2(i, t));
+        const size_t rbm = g->mode == kFp32Fast ? 4 : 8;
+        std::vector<int2>& tl = d.tile_items > stage_slots(rbm) ? wide_tiles : tiles;
+        for (int t = 0; t < d.tiles; ++t) tl.push_back(make_int2(i, t));
         for (int ch = 0; ch < (d.nkeys + kColThreads - 1) / kColThreads; ++ch)
             for (int sgi = 0; sgi < d.nseg; ++sgi) cols.push_back(make_int4(i, ch, sgi, 0));
         max_cc = std::max(max_cc, d.nkeys);
@@ -559,7 +561,12 @@ int build_lane(dsmc_group* g, Lane& lane) {
             cap = std::max(cap, want);
         }
     }
+    // the two kinds of tile are launched separately, each list striped
+    // over the XCDs on its own
     tiles = xcd_stripes(tiles);
+    const int n_narrow = (int)tiles.size();
+    wide_tiles = xcd_stripes(wide_tiles);
+    tiles.insert(tiles.end(), wide_tiles.begin(), wide_tiles.end());
     cblocks = xcd_stripes(cblocks);
     gblocks = xcd_stripes(gblocks);
     // fit the fast-collide staging area into the device's LDS
@@ -578,6 +585,12 @@ int build_lane(dsmc_group* g, Lane& lane) {
     for (const InstDesc& d : descs) any_staged |= d.tile_items <= stage_max;
     if (!any_staged || scatter_lds_bytes((Mode)g->mode, max_cc, stage_max) > (size_t)max_lds)
         stage_max = 0;
+    // the move-scatter's LDS: per-wavefront tables (and staging) for tiles it
+    // holds in registers, the chunk layout for larger tiles
+    const size_t scatter_lds = scatter_lds_bytes((Mode)g->mode, max_cc, stage_max);
+    const size_t wide_lds = wide_scatter_lds_bytes((Mode)g->mode, max_cc);
+    if (!wide_tiles.empty() && wide_lds > (size_t)max_lds)
+        return fail(&g->err, DSMC_ERR_INVALID_ARG, "sort keys exceed the LDS tables of the scatter");
     if (!all_small || resident_lds_bytes((Mode)g->mode, resident_cap) > (size_t)resident_max_lds())
         resident.clear();
     // the column scans in one workgroup per instance when every count matrix is small
@@ -629,6 +642,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
     w.n_inst = n;
     w.tiles = d_tiles;
     w.n_tiles = (int)tiles.size();
+    w.n_narrow = n_narrow;
     w.cols = d_cols;
     w.n_cols = (int)cols.size();
     w.cblocks = d_cb;
@@ -638,6 +652,8 @@ int build_lane(dsmc_group* g, Lane& lane) {
     w.group_cap = group_cap;
     w.max_cc = max_cc;
     w.stage_max = stage_max;
+    w.scatter_lds = scatter_lds;
+    w.wide_lds = wide_lds;
     w.fast_cap = cap;
     w.has_open = has_open;
     w.resident = d_res;

@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # kernel name prefix -> step slot (the slots of dsmc_profile_step)
 PHASE_OF = (("k_count", "count"), ("k_colsum", "colsum"), ("k_scan_small", "scan"),
             ("k_scan", "scan"), ("k_colprefix", "colprefix"), ("k_move_scatter", "move_scatter"),
+            ("k_move_scatter_wide", "move_scatter"),
             ("k_collide_bucket", "collide"), ("k_collide_fast", "collide"),
             ("k_collide_det", "collide"), ("k_resident", "collide"),
             ("k_finalize", "finalize"))

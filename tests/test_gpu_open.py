@@ -33,13 +33,14 @@ def _open(D, prec, **kw):
     return Params(**base)
 
 
-@pytest.mark.parametrize("ppc,n_sub", [(40, 1), (300, 1), (60, 2)])
-def test_open_patch_bit_exact_with_oracle(D, ppc, n_sub):
+@pytest.mark.parametrize("ppc,n_sub,cells", [(40, 1, 30), (300, 1, 30), (60, 2, 30), (500, 1, 300)])
+def test_open_patch_bit_exact_with_oracle(D, ppc, n_sub, cells):
     """FP64 deterministic: injections, removals, states, cell tables, sums
     and the open-boundary counters equal the oracle's to the last bit, across
-    an inflow change."""
-    p = _open(D, D.DSMC_FP64_DETERMINISTIC, particles_per_cell=ppc, n_sub=n_sub)
-    _say(f"open det parity: ppc {ppc}, n_sub {n_sub}")
+    an inflow change.  The 300-cell patch (1.5e5 particles) sorts in tiles
+    larger than the move-scatter's registers hold."""
+    p = _open(D, D.DSMC_FP64_DETERMINISTIC, particles_per_cell=ppc, n_sub=n_sub, n_cells=cells)
+    _say(f"open det parity: ppc {ppc}, n_sub {n_sub}, cells {cells}")
     o = oracle.Oracle(p)
     with D.Solver(p) as g:
         for (u, dudy, steps) in ((0.08, 0.3, 40), (0.11, -0.2, 35)):

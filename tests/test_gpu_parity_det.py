@@ -198,6 +198,34 @@ def test_crafted_sort_inputs(D):
         assert np.array_equal(cnt, ocnt) and np.array_equal(off, ooff)
 
 
+def test_wide_tiles_from_unsorted_state_bit_exact(D):
+    """Tiles larger than the move-scatter holds in registers (300 cells of 500:
+    1280-slot tiles, over the 1024 slots the FP64 registers hold) are walked
+    in chunks ranked 64 keys per pass.  From a state in random slot order every
+    chunk spans all 300 keys (five passes), a few cells are crowded and many
+    empty; two full steps must still equal the oracle bit for bit."""
+    p = Params(kn=0.3, body_force=0.01, n_cells=300, particles_per_cell=500, seed=27,
+               n_transient=0, precision=FP64_DETERMINISTIC)
+    o = oracle.Oracle(p)
+    rng = np.random.default_rng(11)
+    y = rng.random(o.N)
+    crowd = rng.random(o.N) < 0.3
+    y[crowd] = 0.4 + 0.002 * rng.random(int(crowd.sum()))
+    y[(y > 0.6) & (y < 0.75)] = 0.9
+    vx, vy, vz = rng.normal(size=(3, o.N))
+    o.set_particles(y=y, vx=vx, vy=vy, vz=vz)
+    with D.Solver(p) as g:
+        g.set_state(y, vx, vy, vz, step=0)
+        prof = g.profile(1)
+        o.step(1)
+        assert prof["move_scatter"] > 0
+        g.step(1)
+        o.step(1)
+        assert_same_state(g, o, "unsorted")
+        assert_same_cells(g, o, "unsorted")
+        assert np.array_equal(g.sample(raw=True)["raw"], o.acc())
+
+
 def test_torch_arena_and_stream(D):
     import torch
     p = _det(CONFIG0, n_transient=0, seed=21)

@@ -636,8 +636,8 @@ def test_moment_sums_match_the_particle_state(D, prec_name, ppc):
 @pytest.mark.parametrize("prec_name", ["DSMC_FP32_FAST", "DSMC_FP64_FAST"])
 def test_large_tiles_equal_held_tiles(D, prec_name):
     """Instances with full collision cells sort by cell.  A tile larger than
-    the move-scatter holds in registers is counted from the position-only
-    flight first and then moved and placed round by round; tiles eight times
+    the move-scatter holds in registers is walked in chunks, each ranked over
+    the workgroup and laid out in LDS before it is written; tiles eight times
     larger than the automatic ones (held, and at FP64 staged) take that path,
     at low Kn and at high Kn, where particles cross many cells per step.
     Every state, cell table and window sum equals the automatic tiles' bit
