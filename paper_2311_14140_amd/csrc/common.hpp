@@ -17,11 +17,15 @@ constexpr int kColThreads = 256;       // cells per workgroup of the column-scan
 constexpr int kScanThreads = 1024;     // threads of the per-instance scan kernel
 constexpr int kSegTiles = 32;          // tiles per column-scan segment
 constexpr int kCountScanEntries = 8192;  // largest count matrix (tiles x keys) scanned in LDS
-constexpr int kClaimTable = 1024;      // per-wavefront claim table of the fast collide
 constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
 constexpr int kCoopMin = 256;          // cells this full are collided by a whole workgroup
 constexpr int kGroupTableFactor = 8;   // claim-table entries per lane of a small-cell group
-constexpr int kCoopTable = kFastWaves * kClaimTable;  // its claim table (the wave tables together)
+// wavefronts of a workgroup-collide workgroup: 4, or 8 when its staged
+// block takes more than half of a CU's LDS (then no second workgroup fits
+// beside it, and the extra wavefronts hide latency instead); its claim table
+// has 1024 entries per wavefront
+constexpr int kCoopWaves = 4, kCoopWavesAlone = 8;
+constexpr int kCoopTablePerWave = 1024;
 constexpr int kMaxCellsPerKey = 128;   // cells of one sort bucket (a power of two up to this)
 constexpr int kResidentKeys = 256;     // sort keys of an instance stepped by one workgroup
 constexpr int kResidentWaves = 16;     // wavefronts of that workgroup

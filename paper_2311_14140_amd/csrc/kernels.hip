@@ -1408,17 +1408,23 @@ __device__ __forceinline__ void run_candidate(Pend<R>& p, Stream& st, R crmr, V 
 }
 
 struct CoopShared {
-    int idle[kFastWaves];
-    double mx[kFastWaves];
-    uint32_t coll[kFastWaves];
-    double mom[kFastWaves][kMoments];
+    int idle[kCoopWavesAlone];
+    double mx[kCoopWavesAlone];
+    uint32_t coll[kCoopWavesAlone];
+    double mom[kCoopWavesAlone][kMoments];
 };
 
 // NTC of one cell by the whole workgroup (rounds of blockDim candidates).
-// Every thread of the workgroup must call it.
+// Every thread of the workgroup must call it.  A claim is the candidate's
+// number with the round's stamp above it (255 minus the round number mod
+// 256, in the top byte), so a claim left from an earlier round is larger
+// than any of this round's and the table needs no clearing between rounds;
+// it is cleared when the stamps wrap (rnd counts the workgroup's rounds over
+// all its cells).  A cell with 2^24 candidates or more claims with plain
+// numbers and clears its claims after every round.
 template <class R, class V>
 __device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, V vx, V vy, V vz,
-                         uint32_t* tab, CoopShared& sh) {
+                         uint32_t* tab, int tab_mask, CoopShared& sh, int& rnd) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const unsigned long long lt = lanes_below(lane);
     const double crm0 = d.crmax[c];
@@ -1434,6 +1440,12 @@ __device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, V 
     p.i = p.j = 0;
     p.acc = R(0);
     Stream st(d.key0, d.key1, s, (uint32_t)c, 0u, kTagColl);
+    const bool stamped = M < (int64_t)(1 << 24);
+    if (!stamped) {
+        // claims of stamped cells before this one may remain
+        for (int i = threadIdx.x; i <= tab_mask; i += blockDim.x) tab[i] = 0xFFFFFFFFu;
+        __syncthreads();
+    }
     for (;;) {
         const bool idle = p.k < 0;
         const unsigned long long im = __ballot(idle);
@@ -1454,21 +1466,33 @@ __device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, V 
             if (k < M) draw_candidate<R>(d, s, c, nc, k, p, st);
         }
         next += tot;
+        if (stamped && (rnd & 255) == 0 && rnd > 0) {
+            // the stamps wrap: every check of the last round is done (the
+            // barrier above), so the table can be cleared before this
+            // round's claims
+            for (int i = threadIdx.x; i <= tab_mask; i += blockDim.x) tab[i] = 0xFFFFFFFFu;
+            __syncthreads();
+        }
         const bool active = p.k >= 0;
-        const int hi = p.i & (kCoopTable - 1), hj = p.j & (kCoopTable - 1);
+        const int hi = p.i & tab_mask, hj = p.j & tab_mask;
+        const uint32_t claim = stamped ? ((255u - (uint32_t)(rnd & 255)) << 24) | (uint32_t)p.k : (uint32_t)p.k;
         if (active) {
-            atomicMin(&tab[hi], (uint32_t)p.k);
-            atomicMin(&tab[hj], (uint32_t)p.k);
+            atomicMin(&tab[hi], claim);
+            atomicMin(&tab[hj], claim);
         }
         __syncthreads();
-        const bool win = active && tab[hi] == (uint32_t)p.k && tab[hj] == (uint32_t)p.k;
-        __syncthreads();
-        if (active) {
-            tab[hi] = 0xFFFFFFFFu;
-            tab[hj] = 0xFFFFFFFFu;
+        const bool win = active && tab[hi] == claim && tab[hj] == claim;
+        if (!stamped) {
+            __syncthreads();
+            if (active) {
+                tab[hi] = 0xFFFFFFFFu;
+                tab[hj] = 0xFFFFFFFFu;
+            }
         }
+        ++rnd;
         if (win) run_candidate<R, V>(p, st, crmr, vx, vy, vz, o, lane_max, lane_coll);
     }
+    if (!stamped) rnd = 0;  // the table is clear again
     double mx = (double)lane_max;
     uint32_t cc = lane_coll;
 #pragma unroll
@@ -1518,8 +1542,15 @@ __device__ __forceinline__ void cell_moments(V vx, V vy, V vz, int o, int nc, in
 template <class R, class V>
 __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int c0, int c1,
                                               int s0, V vx, V vy, V vz, uint32_t* claims,
-                                              CoopShared& sh, bool do_collide, bool sample) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+                                              int tab_mask, CoopShared& sh, bool do_collide,
+                                              bool sample) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the sampling sums are added by the first kCoopWaves wavefronts in the
+    // same order whatever the workgroup's width, so that the width (chosen
+    // per launch from the LDS a block needs) changes no sum
+    constexpr int nt = 64 * kCoopWaves;
+    const bool adds = (int)threadIdx.x < nt;
+    int rnd = 0;  // NTC rounds since the claim table was last clear
     for (int c = c0; c < c1; ++c) {
         const int nc = d.count[c];
         const int o = d.offset[c] - s0;
@@ -1527,22 +1558,24 @@ __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int
         // barrier keeps every read ahead of the first collision's writes
         double pre = 0.0;
         if (sample) {
-            for (int q = (int)threadIdx.x; q < nc; q += (int)blockDim.x)
-                pre += (double)vx[o + q] * (double)vy[o + q];
+            if (adds)
+                for (int q = (int)threadIdx.x; q < nc; q += nt) pre += (double)vx[o + q] * (double)vy[o + q];
             __syncthreads();
         }
-        if (do_collide && nc >= 2) coop_ntc<R, V>(d, s, c, nc, o, vx, vy, vz, claims, sh);
+        if (do_collide && nc >= 2) coop_ntc<R, V>(d, s, c, nc, o, vx, vy, vz, claims, tab_mask, sh, rnd);
         if (sample) {
-            double tot[kMoments];
-            cell_moments<R, V>(vx, vy, vz, o, nc, (int)threadIdx.x, (int)blockDim.x, pre, tot);
-            if (lane == 0)
-                for (int k = 0; k < kMoments; ++k) sh.mom[wv][k] = tot[k];
+            if (adds) {
+                double tot[kMoments];
+                cell_moments<R, V>(vx, vy, vz, o, nc, (int)threadIdx.x, nt, pre, tot);
+                if (lane == 0)
+                    for (int k = 0; k < kMoments; ++k) sh.mom[wv][k] = tot[k];
+            }
             __syncthreads();
             if (threadIdx.x == 0) {
                 double* a = d.acc + c;
                 for (int k = 0; k < kMoments; ++k) {
                     double t = sh.mom[0][k];
-                    for (int q = 1; q < nw; ++q) t += sh.mom[q][k];
+                    for (int q = 1; q < kCoopWaves; ++q) t += sh.mom[q][k];
                     unsafeAtomicAdd(&a[(size_t)k * d.Cc], t);  // one writer per cell: no read needed
                 }
             }
@@ -1551,14 +1584,15 @@ __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int
     }
 }
 
-template <class R>
-__global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc* __restrict__ descs,
+template <class R, int W>
+__global__ __launch_bounds__(64 * W) void k_collide_fast(const InstDesc* __restrict__ descs,
                                                                  const int4* __restrict__ work,
                                                                  int cap, int do_collide) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ CoopShared sh;
     uint32_t* claims = (uint32_t*)smem;
-    R* lds_v = (R*)(claims + kCoopTable);
+    constexpr int kTable = W * kCoopTablePerWave;
+    R* lds_v = (R*)(claims + kTable);
     const int4 w = work[blockIdx.x];
     const InstDesc& d = descs[w.x];
     const int c0 = w.y, c1 = w.z;
@@ -1567,7 +1601,7 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
     const P4<R> g = particles<R>(d, (int)(s & 1));
     const int s0 = d.offset[c0];
     const int n = d.offset[c1 - 1] + d.count[c1 - 1] - s0;
-    for (int i = threadIdx.x; i < kCoopTable; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
+    for (int i = threadIdx.x; i < kTable; i += blockDim.x) claims[i] = 0xFFFFFFFFu;
     if (n <= cap) {
         R* vx = lds_v;
         R* vy = lds_v + cap;
@@ -1600,7 +1634,8 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
             }
         }
         __syncthreads();
-        collide_cells<R, R*>(d, (uint32_t)s, c0, c1, s0, vx, vy, vz, claims, sh, do_collide, sample);
+        collide_cells<R, R*>(d, (uint32_t)s, c0, c1, s0, vx, vy, vz, claims, kTable - 1, sh, do_collide,
+                             sample);
         __syncthreads();
         if (do_collide) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -1613,7 +1648,7 @@ __global__ __launch_bounds__(64 * kFastWaves) void k_collide_fast(const InstDesc
         // a block fuller than the staging room works on global memory
         __syncthreads();
         collide_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, s0, g.vx + s0, g.vy + s0, g.vz + s0,
-                                  claims, sh, do_collide, sample);
+                                  claims, kTable - 1, sh, do_collide, sample);
     }
 }
 
@@ -2410,6 +2445,7 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
     // a tuning may raise the dynamic LDS of the particle and collide kernels
     // above what they use, to cap the workgroups that share a CU
     auto lds = [&](size_t need) { return need > w.lds_floor ? need : w.lds_floor; };
+    auto coop_lds = [&](size_t need) { return need > w.lds_floor_coop ? need : w.lds_floor_coop; };
     const size_t hist_lds = lds((size_t)w.max_cc * sizeof(int));
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
@@ -2473,10 +2509,16 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
             hipLaunchKernelGGL(k_collide_det, dim3(w.n_gblocks), dim3(64), 0, st, w.desc, w.gblocks,
                                do_collide);
         } else {
-            if (w.n_cblocks)
-                hipLaunchKernelGGL((k_collide_fast<R>), dim3(w.n_cblocks), dim3(64 * kFastWaves),
-                                   lds(fast_collide_lds_bytes(mode, w.fast_cap)), st, w.desc, w.cblocks,
-                                   w.fast_cap, do_collide);
+            if (w.n_cblocks) {
+                const size_t clds = coop_lds(fast_collide_lds_bytes(mode, w.fast_cap, w.coop_waves));
+                if (w.coop_waves == kCoopWavesAlone)
+                    hipLaunchKernelGGL((k_collide_fast<R, kCoopWavesAlone>), dim3(w.n_cblocks),
+                                       dim3(64 * kCoopWavesAlone), clds, st, w.desc, w.cblocks, w.fast_cap,
+                                       do_collide);
+                else
+                    hipLaunchKernelGGL((k_collide_fast<R, kCoopWaves>), dim3(w.n_cblocks), dim3(64 * kCoopWaves),
+                                       clds, st, w.desc, w.cblocks, w.fast_cap, do_collide);
+            }
             if (w.n_gblocks)
                 hipLaunchKernelGGL((k_collide_bucket<R>), dim3(w.n_gblocks), dim3(64 * kFastWaves),
                                    lds(bucket_collide_lds_bytes(mode, w.group_cap)), st, w.desc,
@@ -2525,9 +2567,9 @@ size_t bucket_collide_lds_bytes(Mode mode, int cap) {
            (size_t)2 * kMaxCellsPerKey * (sizeof(double) + sizeof(int)) + 3 * (size_t)cap * rb;
 }
 
-size_t fast_collide_lds_bytes(Mode mode, int cap) {
+size_t fast_collide_lds_bytes(Mode mode, int cap, int waves) {
     const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
-    return (size_t)kCoopTable * sizeof(uint32_t) + 3 * (size_t)cap * rb;
+    return (size_t)waves * kCoopTablePerWave * sizeof(uint32_t) + 3 * (size_t)cap * rb;
 }
 
 void launch_init(const InstDesc& d, const InstDesc* d_desc, Mode mode, hipStream_t s) {
@@ -2553,8 +2595,10 @@ hipError_t configure_kernels(size_t max_dynamic_lds) {
         const hipError_t r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (r != hipSuccess) e = r;
     };
-    set((const void*)k_collide_fast<float>);
-    set((const void*)k_collide_fast<double>);
+    set((const void*)k_collide_fast<float, kCoopWaves>);
+    set((const void*)k_collide_fast<double, kCoopWaves>);
+    set((const void*)k_collide_fast<float, kCoopWavesAlone>);
+    set((const void*)k_collide_fast<double, kCoopWavesAlone>);
     set((const void*)k_collide_bucket<float>);
     set((const void*)k_collide_bucket<double>);
     set((const void*)k_move_hist<float, true>);

@@ -29,6 +29,7 @@ struct Work {
     size_t scatter_lds;     // dynamic LDS of the move-scatter
     size_t wide_lds;        // and of its wide-tile kernel
     int fast_cap;           // particles a fast-collide workgroup stages in LDS
+    int coop_waves;         // wavefronts of a fast-collide workgroup
     int has_open;           // some instance has an open boundary (open-boundary kernel variants)
     // resident lanes (every member small): (instance, G) per workgroup of
     // k_resident, which then runs whole steps instead of the lists above
@@ -42,6 +43,7 @@ struct Work {
     // least this many bytes (0: what they use): it caps how many of their
     // workgroups share a CU, the occupancy knob of the launch-shape tuning
     size_t lds_floor;
+    size_t lds_floor_coop;  // the same cap for the workgroup collide's larger workgroups
 };
 
 void launch_init(const InstDesc& d, const InstDesc* d_desc, Mode mode, hipStream_t s);
@@ -68,7 +70,7 @@ void launch_gather_status(const InstDesc* d_desc, int n_inst, int32_t* d_out, hi
 void launch_finalize_gather(const InstDesc* const* d_descs, const int64_t* d_off, double* d_stage,
                             int n_inst, hipStream_t s);
 void launch_reset_window_gather(const InstDesc* const* d_descs, int n_inst, hipStream_t s);
-size_t fast_collide_lds_bytes(Mode mode, int cap);
+size_t fast_collide_lds_bytes(Mode mode, int cap, int waves);
 size_t bucket_collide_lds_bytes(Mode mode, int cap);
 size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max);
 // LDS of the move-scatter's kernel for tiles larger than its registers hold.

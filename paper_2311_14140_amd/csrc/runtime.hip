@@ -572,9 +572,15 @@ int build_lane(dsmc_group* g, Lane& lane) {
     // fit the fast-collide staging area into the device's LDS
     const size_t rb = g->mode == kFp32Fast ? 4 : 8;
     const int max_lds = device_max_lds();
-    const size_t fixed = (size_t)kCoopTable * 4 + 1024;  // claim table + static shared
+    const size_t fixed = (size_t)kCoopWaves * kCoopTablePerWave * 4 + 1024;  // claim table + static shared
     const int cap_max = (int)(((size_t)max_lds - fixed) / (3 * rb));
     cap = std::min(cap, cap_max);
+    // a block that leaves no room for a second workgroup on its CU gets the
+    // larger workgroup, if its larger claim table still fits
+    int coop_waves = kCoopWaves;
+    if (2 * (fast_collide_lds_bytes((Mode)g->mode, cap, kCoopWaves) + 1024) > (size_t)cu_lds_bytes() &&
+        fast_collide_lds_bytes((Mode)g->mode, cap, kCoopWavesAlone) + 1024 <= (size_t)max_lds)
+        coop_waves = kCoopWavesAlone;
     const size_t gfixed = bucket_collide_lds_bytes((Mode)g->mode, 0) + 256;  // + static shared
     group_cap = std::min(group_cap, (int)(((size_t)max_lds - gfixed) / (3 * rb)));
     if ((size_t)max_cc * 4 * kScatterWaves > (size_t)max_lds)
@@ -655,6 +661,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
     w.scatter_lds = scatter_lds;
     w.wide_lds = wide_lds;
     w.fast_cap = cap;
+    w.coop_waves = coop_waves;
     w.has_open = has_open;
     w.resident = d_res;
     w.n_resident = (int)resident.size();
@@ -665,10 +672,15 @@ int build_lane(dsmc_group* g, Lane& lane) {
     // static shared variables and allocation granularity) lets at most k
     // share a CU
     w.lds_floor = 0;
+    w.lds_floor_coop = 0;
     if (g->waves_per_cu > 0) {
-        const int per_cu = std::max(1, g->waves_per_cu / 4);
-        const int floor_bytes = cu_lds_bytes() / per_cu - 2048;
-        w.lds_floor = (size_t)std::max(0, std::min(floor_bytes, max_lds));
+        auto floor_of = [&](int waves_per_group) {
+            const int per_cu = std::max(1, g->waves_per_cu / waves_per_group);
+            const int floor_bytes = cu_lds_bytes() / per_cu - 2048;
+            return (size_t)std::max(0, std::min(floor_bytes, max_lds));
+        };
+        w.lds_floor = floor_of(4);
+        w.lds_floor_coop = floor_of(coop_waves);
     }
     return DSMC_OK;
 }
