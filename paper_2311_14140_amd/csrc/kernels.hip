@@ -1523,11 +1523,14 @@ __device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, V 
 // Sampling sums of one cell: per lane over a strided share of the cell, then
 // a fixed butterfly over the wavefront (and, in workgroup mode, the wavefront
 // partials added in wavefront order).
-template <class R, class V>
+template <class R, class V, int U = 1>
 __device__ __forceinline__ void cell_moments(V vx, V vy, V vz, int o, int nc, int first,
                                              int stride, double pre, double tot[kMoments]) {
     Mom m;
     mom_zero(m);
+    // unrolled U times (when registers allow) so that the next records'
+    // loads overlap this one's sums; the order of the additions is unchanged
+#pragma unroll U
     for (int q = first; q < nc; q += stride)
         mom_add(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
     m.s[kMomPreXY] = pre;
@@ -1539,7 +1542,7 @@ __device__ __forceinline__ void cell_moments(V vx, V vy, V vz, int o, int nc, in
 // workgroup.  Inlined once for velocities in LDS and once for velocities in
 // global memory, so each copy addresses its memory directly (LDS accesses
 // become ds_* instructions rather than flat ones).
-template <class R, class V>
+template <class R, class V, int U>
 __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int c0, int c1,
                                               int s0, V vx, V vy, V vz, uint32_t* claims,
                                               int tab_mask, CoopShared& sh, bool do_collide,
@@ -1558,15 +1561,17 @@ __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int
         // barrier keeps every read ahead of the first collision's writes
         double pre = 0.0;
         if (sample) {
-            if (adds)
+            if (adds) {
+#pragma unroll U
                 for (int q = (int)threadIdx.x; q < nc; q += nt) pre += (double)vx[o + q] * (double)vy[o + q];
+            }
             __syncthreads();
         }
         if (do_collide && nc >= 2) coop_ntc<R, V>(d, s, c, nc, o, vx, vy, vz, claims, tab_mask, sh, rnd);
         if (sample) {
             if (adds) {
                 double tot[kMoments];
-                cell_moments<R, V>(vx, vy, vz, o, nc, (int)threadIdx.x, nt, pre, tot);
+                cell_moments<R, V, U>(vx, vy, vz, o, nc, (int)threadIdx.x, nt, pre, tot);
                 if (lane == 0)
                     for (int k = 0; k < kMoments; ++k) sh.mom[wv][k] = tot[k];
             }
@@ -1634,8 +1639,10 @@ __global__ __launch_bounds__(64 * W) void k_collide_fast(const InstDesc* __restr
             }
         }
         __syncthreads();
-        collide_cells<R, R*>(d, (uint32_t)s, c0, c1, s0, vx, vy, vz, claims, kTable - 1, sh, do_collide,
-                             sample);
+        // a workgroup alone on its CU has registers to spare for unrolling
+        // the sampling loops; four-wavefront ones keep more workgroups
+        collide_cells<R, R*, W == kCoopWavesAlone ? 4 : 1>(d, (uint32_t)s, c0, c1, s0, vx, vy, vz, claims,
+                                                           kTable - 1, sh, do_collide, sample);
         __syncthreads();
         if (do_collide) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -1647,7 +1654,7 @@ __global__ __launch_bounds__(64 * W) void k_collide_fast(const InstDesc* __restr
     } else {
         // a block fuller than the staging room works on global memory
         __syncthreads();
-        collide_cells<R, gptr<R>>(d, (uint32_t)s, c0, c1, s0, g.vx + s0, g.vy + s0, g.vz + s0,
+        collide_cells<R, gptr<R>, 1>(d, (uint32_t)s, c0, c1, s0, g.vx + s0, g.vy + s0, g.vz + s0,
                                   claims, kTable - 1, sh, do_collide, sample);
     }
 }
