@@ -383,8 +383,13 @@ __global__ __launch_bounds__(kColThreads) void k_colsum(const InstDesc* __restri
     if (c >= nk) return;
     const int t0 = w.z * kSegTiles, t1 = min(t0 + kSegTiles, d.tiles);
     const gptr<int32_t> cnt = gmem(d.counts);
+    // every load of the segment issued before the first is used
+    int v[kSegTiles];
+#pragma unroll
+    for (int u = 0; u < kSegTiles; ++u) v[u] = t0 + u < t1 ? cnt[(size_t)(t0 + u) * nk + c] : 0;
     int sum = 0;
-    for (int t = t0; t < t1; ++t) sum += cnt[(size_t)t * nk + c];
+#pragma unroll
+    for (int u = 0; u < kSegTiles; ++u) sum += v[u];
     d.segsum[(size_t)w.z * nk + c] = sum;
 }
 
@@ -435,34 +440,33 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(const InstDesc* __restric
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (do_scan) {
         if (tid == 0) sh_used = book_injections(d);
-        __syncthreads();
         const int Cc = d.nkeys, nseg = d.nseg;
         const gptr<int32_t> seg = gmem(d.segsum);
-        const int per = (Cc + kScanThreads - 1) / kScanThreads;
-        const int c0 = min(tid * per, Cc), c1 = min(c0 + per, Cc);
-        int local = 0;
-        for (int c = c0; c < c1; ++c) {
-            // column sums of the segments -> exclusive prefix over segments
+        // column sums of the segments -> exclusive prefix over segments, key
+        // c = tid + j * kScanThreads (a wavefront's loads are 64 adjacent
+        // keys), 32 segments' loads in flight at a time
+        constexpr int B = 32;
+        for (int c = tid; c < Cc; c += kScanThreads) {
             int tot = 0;
-            int g = 0;
-            for (; g + 8 <= nseg; g += 8) {
-                int v[8];
+            for (int g = 0; g < nseg; g += B) {
+                int v[B];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = seg[(size_t)(g + u) * Cc + c];
+                for (int u = 0; u < B; ++u) v[u] = g + u < nseg ? seg[(size_t)(g + u) * Cc + c] : 0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    seg[(size_t)(g + u) * Cc + c] = tot;
+                for (int u = 0; u < B; ++u) {
+                    if (g + u < nseg) seg[(size_t)(g + u) * Cc + c] = tot;
                     tot += v[u];
                 }
             }
-            for (; g < nseg; ++g) {
-                const int v = seg[(size_t)g * Cc + c];
-                seg[(size_t)g * Cc + c] = tot;
-                tot += v;
-            }
             d.kcount[c] = tot;
-            local += tot;
         }
+        // the key totals are read back by other threads below
+        __threadfence_block();
+        __syncthreads();
+        const int per = (Cc + kScanThreads - 1) / kScanThreads;
+        const int c0 = min(tid * per, Cc), c1 = min(c0 + per, Cc);
+        int local = 0;
+        for (int c = c0; c < c1; ++c) local += d.kcount[c];
         const int incl = wave_incl_scan(local, lane);
         if (lane == 63) wsum[wv] = incl;
         __syncthreads();
@@ -502,11 +506,15 @@ __global__ __launch_bounds__(kColThreads) void k_colprefix(const InstDesc* __res
     int run = d.koffset[c] + gmem(d.segsum)[(size_t)w.z * nk + c];
     const int t0 = w.z * kSegTiles, t1 = min(t0 + kSegTiles, d.tiles);
     const gptr<int32_t> cnt = gmem(d.counts);
-    for (int t = t0; t < t1; ++t) {
-        const gptr<int32_t> e = cnt + (size_t)t * nk + c;
-        const int v = *e;
-        *e = run;
-        run += v;
+    // the segment's counts are all loaded before the first base is stored
+    // (a load after a store to the same array waited for it)
+    int v[kSegTiles];
+#pragma unroll
+    for (int u = 0; u < kSegTiles; ++u) v[u] = t0 + u < t1 ? cnt[(size_t)(t0 + u) * nk + c] : 0;
+#pragma unroll
+    for (int u = 0; u < kSegTiles; ++u) {
+        if (t0 + u < t1) cnt[(size_t)(t0 + u) * nk + c] = run;
+        run += v[u];
     }
 }
 
