@@ -845,21 +845,35 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter_wide(const In
     __syncthreads();
     const unsigned long long lt = lanes_below(lane);
     int bad = 0, pass = 0, nbase = 0;
+    // the next chunk's records are loaded while this one is ranked and
+    // written (the barriers wait for LDS operations only)
+    R ny[J], nx[J], nv[J], nz[J];
+    auto load_chunk = [&](int cb) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int i = cb + j * kParticleThreads + tid;
+            ny[j] = nx[j] = nv[j] = nz[j] = R(0);
+            if (i < end) {
+                ny[j] = src.y[i];
+                nx[j] = src.vx[i];
+                nv[j] = src.vy[i];
+                nz[j] = src.vz[i];
+            }
+        }
+    };
+    if (start < end) load_chunk(start);
     for (int cb = start, ci = 0; cb < end; cb += C, ++ci) {
         const int par = 2 * (ci & 1);
         R ry[J], rx[J], rv[J], rz[J];
         int key[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            const int i = cb + j * kParticleThreads + tid;
-            ry[j] = rx[j] = rv[j] = rz[j] = R(0);
-            if (i < end) {
-                ry[j] = src.y[i];
-                rx[j] = src.vx[i];
-                rv[j] = src.vy[i];
-                rz[j] = src.vz[i];
-            }
+            ry[j] = ny[j];
+            rx[j] = nx[j];
+            rv[j] = nv[j];
+            rz[j] = nz[j];
         }
+        if (cb + C < end) load_chunk(cb + C);
         int kmn = INT32_MAX, kmx = -1;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
