@@ -1611,6 +1611,21 @@ __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int
     }
 }
 
+// Copy n values from global memory to LDS with loads that write LDS
+// directly (global_load_lds_dword: each lane of a wavefront moves one dword to
+// the wavefront's LDS base, taken from the LDS pointer, plus four times its
+// lane number).  The caller waits for vmcnt(0) before the data is read.
+template <class R>
+__device__ __forceinline__ void stage_to_lds(gptr<R> src, R* dst, int n) {
+    const int nd = n * (int)(sizeof(R) / 4);
+    const int lane = threadIdx.x & 63;
+    const gptr<uint32_t> s = (gptr<uint32_t>)src;
+    uint32_t* d = (uint32_t*)dst;
+    for (int i = threadIdx.x; i < nd; i += blockDim.x)
+        __builtin_amdgcn_global_load_lds((const void*)(s + i),
+                                         (__attribute__((address_space(3))) void*)(d + (i - lane)), 4, 0, 0);
+}
+
 template <class R, int W>
 __global__ __launch_bounds__(64 * W) void k_collide_fast(const InstDesc* __restrict__ descs,
                                                                  const int4* __restrict__ work,
@@ -1633,33 +1648,13 @@ __global__ __launch_bounds__(64 * W) void k_collide_fast(const InstDesc* __restr
         R* vx = lds_v;
         R* vy = lds_v + cap;
         R* vz = lds_v + 2 * cap;
-        // staged in batches of U records per thread, all of a batch's loads
-        // issued before its first LDS store: with one large cell per CU
-        // there are few other wavefronts to hide a load's latency, and a
-        // load-store pair per iteration waited for each load in turn
-        constexpr int U = 8;
-        for (int b = (int)threadIdx.x; b < n; b += U * (int)blockDim.x) {
-            R tx[U], ty[U], tz[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = b + u * (int)blockDim.x;
-                tx[u] = ty[u] = tz[u] = R(0);
-                if (i < n) {
-                    tx[u] = g.vx[s0 + i];
-                    ty[u] = g.vy[s0 + i];
-                    tz[u] = g.vz[s0 + i];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = b + u * (int)blockDim.x;
-                if (i < n) {
-                    vx[i] = tx[u];
-                    vy[i] = ty[u];
-                    vz[i] = tz[u];
-                }
-            }
-        }
+        // staged with loads that write LDS directly: every load of the
+        // block is in flight at once, with no registers held (with one large
+        // cell per CU there are few other wavefronts to hide the latency)
+        stage_to_lds(g.vx + s0, vx, n);
+        stage_to_lds(g.vy + s0, vy, n);
+        stage_to_lds(g.vz + s0, vz, n);
+        __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0): the staged data is in LDS
         __syncthreads();
         // a workgroup alone on its CU has registers to spare for unrolling
         // the sampling loops; four-wavefront ones keep more workgroups

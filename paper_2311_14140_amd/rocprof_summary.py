@@ -3,6 +3,7 @@
     python -m paper_2311_14140_amd.rocprof_summary stats DIR
     python -m paper_2311_14140_amd.rocprof_summary traffic --stats DIR --fetch DIR \\
         --write DIR --tag NAME --workload TEXT [--copy-mib 256] [--json FILE]
+    python -m paper_2311_14140_amd.rocprof_summary issue DIR [DIR ...]
 
 ``stats`` prints the kernel statistics of a ``--kernel-trace --stats -f csv``
 run as a table.  ``traffic`` reads two counter runs (``--pmc FETCH_SIZE`` and
@@ -11,7 +12,11 @@ KiB per dispatch to bytes, scaled by what the same counter reads for a plain
 device copy of known size in the same run (the bench's calibration copy):
 the largest copy dispatch is taken as that copy.  It prints a table per step
 kernel and records the bytes per launch with the hash of the sources in the
-JSON file that bench.py reads for its ``traffic`` field.
+JSON file that bench.py reads for its ``traffic`` field.  ``issue`` reads SQ
+counter runs (``--pmc SQ_...``, any split of the counters over runs) and
+prints, per step kernel averaged over its dispatches, the fraction of its
+wavefronts' cycles spent issuing each kind of instruction or waiting, and
+its instructions per wavefront.
 """
 from __future__ import annotations
 
@@ -26,12 +31,13 @@ from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
-# kernel name prefix -> step slot (the slots of dsmc_profile_step)
+# kernel name prefix -> step slot (the slots of dsmc_profile_step; a resident
+# lane's whole-step kernel is kept apart, as that call reports its share)
 PHASE_OF = (("k_count", "count"), ("k_colsum", "colsum"), ("k_scan_small", "scan"),
             ("k_scan", "scan"), ("k_colprefix", "colprefix"), ("k_move_scatter", "move_scatter"),
             ("k_move_scatter_wide", "move_scatter"),
             ("k_collide_bucket", "collide"), ("k_collide_fast", "collide"),
-            ("k_collide_det", "collide"), ("k_resident", "collide"),
+            ("k_collide_det", "collide"), ("k_resident", "resident"),
             ("k_finalize", "finalize"))
 SOURCES = ("kernels.hip", "runtime.hip", "rng.hpp", "common.hpp", "kernels.hpp")
 
@@ -111,6 +117,36 @@ def copy_scale(values: dict, copy_mib: int) -> float:
     return copy_mib * 1024.0 / max(copies)
 
 
+def cmd_issue(a):
+    per_kernel = defaultdict(lambda: defaultdict(list))
+    for directory in a.dirs:
+        per = defaultdict(float)
+        for r in _rows(directory, "counter_collection.csv"):
+            key = (r.get("Dispatch_Id") or r.get("Correlation_Id"), r["Kernel_Name"], r["Counter_Name"])
+            per[key] += float(r["Counter_Value"])
+        for (_, name, counter), v in per.items():
+            per_kernel[short_name(name)][counter].append(v)
+    for name in sorted(per_kernel):
+        if not phase(name) or phase(name) in ("finalize",):
+            continue
+        m = {c: sum(v) / len(v) for c, v in per_kernel[name].items()}
+        if "SQ_WAVE_CYCLES" in m:
+            wc = m["SQ_WAVE_CYCLES"]
+            parts = [(k, "SQ_ACTIVE_INST_" + k) for k in ("VALU", "LDS", "VMEM", "SCA", "ANY")]
+            parts += [("WAIT_ANY", "SQ_WAIT_ANY"), ("WAIT_INST_ANY", "SQ_WAIT_INST_ANY")]
+            print(f"== {name}")
+            print("  per wave-cycle: " + " ".join(f"{k} {m[c] / wc:.3f}" for k, c in parts if c in m))
+        if "SQ_WAVES" in m:
+            w = m["SQ_WAVES"]
+            parts = [(k, "SQ_INSTS_" + k) for k in ("VALU", "LDS", "SALU", "VMEM_RD", "VMEM_WR", "BRANCH")]
+            line = " ".join(f"{k} {m[c] / w:.0f}" for k, c in parts if c in m)
+            if "SQ_LDS_BANK_CONFLICT" in m and m.get("SQ_INSTS_LDS"):
+                line += f"; bank conflicts per LDS instruction {m['SQ_LDS_BANK_CONFLICT'] / m['SQ_INSTS_LDS']:.3f}"
+            if "SQ_WAVE_CYCLES" not in m:
+                print(f"== {name}")
+            print("  instructions per wavefront: " + line)
+
+
 def cmd_stats(a):
     print("| kernel | calls | total us | average us | % |")
     print("|---|---|---|---|---|")
@@ -179,8 +215,10 @@ def main(argv=None):
     t.add_argument("--workload", required=True)
     t.add_argument("--copy-mib", type=int, default=256)
     t.add_argument("--json", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+    i = sub.add_parser("issue")
+    i.add_argument("dirs", nargs="+")
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "issue": cmd_issue}[a.cmd](a)
 
 
 if __name__ == "__main__":
