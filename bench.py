@@ -367,11 +367,13 @@ def main():
         sub.step(args.warmup)
     sub.sync()
     sub.sample()
-    # one more graph chunk past the warm-up: the step graphs are captured when
-    # a group's lanes are built, and this replays them once before timing
+    # one more graph chunk past the warm-up, right before the timed steps:
+    # it replays the step graphs (captured when a group's lanes are built)
+    # once, and keeps the device busy up to the timed region (after the
+    # host-side window reads above, an idle device ran the first timed
+    # steps some 5% slower)
     sub.step(8)
     sub.sync()
-    sub.sample()
 
     # ---- timed region: K steps, graph-replayed, inputs resident in HBM
     torch.cuda.synchronize()
@@ -381,9 +383,10 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     rate = N * args.steps / el
+    # the window holds the extra chunk and the timed steps
     est = sub.sample()
     n_coll = sum(e["n_collisions"] for e in est)
-    coll_frac = 2.0 * n_coll / (N * args.steps)
+    coll_frac = 2.0 * n_coll / sum(s.N * e["n_sampled_steps"] for s, e in zip(sub.sols, est))
     log(f"timed {args.steps} steps in {el:.4f} s: {rate:.4e} particle-steps/s")
 
     # ---- per-kernel durations: HIP events around every kernel on the

@@ -330,8 +330,10 @@ struct Lane {
     void* d_mem = nullptr;   // device-side work lists
     size_t d_bytes = 0;
     Work work{};
-    hipGraphExec_t gexec = nullptr;  // graph of kGraphSteps steps
-    hipGraph_t graph = nullptr;
+    // graphs of 8, 4, 2 and 1 whole steps (kGraphSizes), so that any number
+    // of steps is replayed from graphs
+    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
     hipStream_t cap_stream = nullptr;
     hipStream_t stream = nullptr;    // own stream when the group has several lanes
     hipEvent_t done = nullptr;
@@ -371,6 +373,7 @@ struct dsmc_group {
 namespace {
 
 constexpr int kGraphSteps = 8;
+constexpr int kGraphSizes[4] = {8, 4, 2, 1};  // steps of a lane's graphs
 constexpr int64_t kResidentChunk = 4096;  // steps per launch of a resident lane
 
 hipStream_t stream_of(const dsmc_handle* h) {
@@ -378,10 +381,12 @@ hipStream_t stream_of(const dsmc_handle* h) {
 }
 
 void drop_graph(Lane& l) {
-    if (l.gexec) (void)hipGraphExecDestroy(l.gexec);
-    if (l.graph) (void)hipGraphDestroy(l.graph);
-    l.gexec = nullptr;
-    l.graph = nullptr;
+    for (int i = 0; i < 4; ++i) {
+        if (l.gexec[i]) (void)hipGraphExecDestroy(l.gexec[i]);
+        if (l.graph[i]) (void)hipGraphDestroy(l.graph[i]);
+        l.gexec[i] = nullptr;
+        l.graph[i] = nullptr;
+    }
 }
 
 void drop_graphs(dsmc_group* g) {
@@ -685,26 +690,30 @@ int build_lane(dsmc_group* g, Lane& lane) {
     return DSMC_OK;
 }
 
-// Capture the lane's graph of kGraphSteps whole steps when the lane is
+// Capture the lane's graphs of 8, 4, 2 and 1 whole steps when the lane is
 // built.  Capture only records the launches (no kernel runs), so the first
-// steps that replay it pay no capture or instantiation.  Resident lanes and
+// steps that replay them pay no capture or instantiation, and a call's
+// steps are all replayed (whole chunks of 8, then at most one graph of each
+// smaller size), never launched one kernel at a time.  Resident lanes and
 // debug phase masks launch directly and have no graph.
 int capture_lane(dsmc_group* g, Lane& l) {
     if (l.members.empty() || l.work.n_resident || g->phase != DSMC_PHASE_ALL) return DSMC_OK;
     if (!l.cap_stream) HIP_TRY(&g->err, hipStreamCreateWithFlags(&l.cap_stream, hipStreamNonBlocking));
-    HIP_TRY(&g->err, hipStreamBeginCapture(l.cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < kGraphSteps; ++k) launch_step(l.work, (Mode)g->mode, g->phase, l.cap_stream);
-    const hipError_t launched = hipGetLastError();
-    hipGraph_t graph = nullptr;
-    const hipError_t ended = hipStreamEndCapture(l.cap_stream, &graph);
-    if (launched != hipSuccess || ended != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return fail(&g->err, DSMC_ERR_DEVICE,
-                    std::string("step graph capture: ") +
-                        hipGetErrorString(launched != hipSuccess ? launched : ended));
+    for (int i = 0; i < 4; ++i) {
+        HIP_TRY(&g->err, hipStreamBeginCapture(l.cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < kGraphSizes[i]; ++k) launch_step(l.work, (Mode)g->mode, g->phase, l.cap_stream);
+        const hipError_t launched = hipGetLastError();
+        hipGraph_t graph = nullptr;
+        const hipError_t ended = hipStreamEndCapture(l.cap_stream, &graph);
+        if (launched != hipSuccess || ended != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(&g->err, DSMC_ERR_DEVICE,
+                        std::string("step graph capture: ") +
+                            hipGetErrorString(launched != hipSuccess ? launched : ended));
+        }
+        l.graph[i] = graph;
+        HIP_TRY(&g->err, hipGraphInstantiate(&l.gexec[i], graph, nullptr, nullptr, 0));
     }
-    l.graph = graph;
-    HIP_TRY(&g->err, hipGraphInstantiate(&l.gexec, graph, nullptr, nullptr, 0));
     return DSMC_OK;
 }
 
@@ -785,7 +794,17 @@ int enqueue_steps(dsmc_group* g, int64_t n_steps) {
     const Mode mode = (Mode)g->mode;
     const int nl = g->n_lanes;
     if (nl > 1) HIP_TRY(&g->err, hipEventRecord(g->fork, g->stream));
-    for (int li = 0; li < nl; ++li) {
+    // resident lanes are enqueued first: each of their workgroups needs most
+    // of a CU's LDS, which a CU has free before the multi-kernel lanes fill
+    // it; enqueued after them, they could only start in the gaps between
+    // those lanes' kernels and finished after them
+    std::vector<int> order;
+    order.reserve(nl);
+    for (int li = 0; li < nl; ++li)
+        if (g->lanes[li].work.n_resident) order.push_back(li);
+    for (int li = 0; li < nl; ++li)
+        if (!g->lanes[li].work.n_resident) order.push_back(li);
+    for (int li : order) {
         Lane& l = g->lanes[li];
         const hipStream_t st = lane_stream(g, l);
         if (nl > 1) HIP_TRY(&g->err, hipStreamWaitEvent(st, g->fork, 0));
@@ -798,12 +817,17 @@ int enqueue_steps(dsmc_group* g, int64_t n_steps) {
             }
             left = 0;
         }
-        // the graph was captured when the lane was built
-        if (l.gexec) {
+        // the graphs were captured when the lane was built
+        if (l.gexec[0]) {
             while (left >= kGraphSteps) {
-                HIP_TRY(&g->err, hipGraphLaunch(l.gexec, st));
+                HIP_TRY(&g->err, hipGraphLaunch(l.gexec[0], st));
                 left -= kGraphSteps;
             }
+            for (int i = 1; i < 4; ++i)
+                if (left >= kGraphSizes[i]) {
+                    HIP_TRY(&g->err, hipGraphLaunch(l.gexec[i], st));
+                    left -= kGraphSizes[i];
+                }
         }
         for (int64_t k = 0; k < left; ++k) {
             launch_step(l.work, mode, g->phase, st);

@@ -102,17 +102,22 @@ def test_full_steps_bit_exact_config0(D):
 
 
 def test_graph_replay_equals_eager_steps(D):
-    """dsmc_step(n >= 8) replays a captured graph; it must equal single steps."""
+    """dsmc_step replays captured graphs of 8, 4, 2 and 1 steps (37 = four
+    8-step graphs, a 4-step and a 1-step one; or 37 one-step graphs); both
+    must equal steps launched kernel by kernel (the profiling call)."""
     p = _det(CONFIG0, n_transient=0, seed=77)
-    with D.Solver(p) as a, D.Solver(p) as b:
+    with D.Solver(p) as a, D.Solver(p) as b, D.Solver(p) as c:
         a.step(37)
         for _ in range(37):
             b.step(1)
-        sa, sb = a.get_state(), b.get_state()
-        for x, y in zip(sa, sb):
+        c.profile(37)
+        sa, sb, sc = a.get_state(), b.get_state(), c.get_state()
+        for x, y, z in zip(sa, sb, sc):
             assert np.array_equal(np.asarray(x), np.asarray(y))
-        ea, eb = a.sample(raw=True), b.sample(raw=True)
+            assert np.array_equal(np.asarray(x), np.asarray(z))
+        ea, eb, ec = a.sample(raw=True), b.sample(raw=True), c.sample(raw=True)
         assert np.array_equal(ea["raw"], eb["raw"])
+        assert np.array_equal(ea["raw"], ec["raw"])
 
 
 def test_window_reset_and_resample(D):
