@@ -36,6 +36,9 @@ constexpr int kScatterRegs32 = 5, kScatterRegs64 = 4;
 // move-scatter walks such a tile in chunks of 256 times this many slots
 constexpr int kWideRecs32 = 4, kWideRecs64 = 2;
 constexpr int kWideKeys = 64;  // sort keys ranked per pass over a chunk (one wavefront's lanes)
+// keys of a wide tile whose next destinations are kept in LDS (from the
+// tile's smallest key on; any beyond use the tile's row in global memory)
+constexpr int kWideRunKeys = 1024;
 
 // Scalars an instance keeps on the device so that a step is the same launch
 // sequence every time (and can be replayed from a graph).
@@ -100,6 +103,7 @@ struct InstDesc {
     void* buf[2][4];
     int32_t* cell;     // N: sort key of each slot (pre-sort order)
     int32_t* counts;   // tiles * nkeys: per-tile histogram, then per-tile scatter bases
+    int32_t* tkeys;    // tiles * 2: smallest and largest sort key in each tile after the move
     int32_t* segsum;   // nseg * nkeys: per-segment column sums, then segment bases
     int32_t* kcount;   // nkeys: particles per key
     int32_t* koffset;  // nkeys: first slot of each key

@@ -726,7 +726,43 @@ __global__ __launch_bounds__(kParticleThreads) void k_count(const InstDesc* __re
         }
     __syncthreads();
     const gptr<int32_t> row = gmem(d.counts) + (size_t)w.y * nk;
-    for (int c = threadIdx.x; c < nk; c += blockDim.x) row[c] = hist[c];
+    constexpr int held = kScatterWaves * 64 * (sizeof(R) == 4 ? kScatterRegs32 : kScatterRegs64);
+    if (d.tile_items <= held) {
+        for (int c = threadIdx.x; c < nk; c += blockDim.x) row[c] = hist[c];
+        return;
+    }
+    // a tile larger than the move-scatter's registers also records its
+    // smallest and largest key, for the wide-tile scatter's tables (an empty
+    // tile records an empty range)
+    int kmn = INT32_MAX, kmx = -1;
+    for (int c = threadIdx.x; c < nk; c += blockDim.x) {
+        const int v = hist[c];
+        row[c] = v;
+        if (v) {
+            kmn = min(kmn, c);
+            kmx = max(kmx, c);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        kmn = min(kmn, __shfl_xor(kmn, o, 64));
+        kmx = max(kmx, __shfl_xor(kmx, o, 64));
+    }
+    __shared__ int kr[2];
+    if (threadIdx.x == 0) {
+        kr[0] = INT32_MAX;
+        kr[1] = -1;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&kr[0], kmn);
+        atomicMax(&kr[1], kmx);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        d.tkeys[2 * w.y] = kr[0];
+        d.tkeys[2 * w.y + 1] = kr[1];
+    }
 }
 
 // The column scans in one workgroup per instance, for lanes whose instances
@@ -808,11 +844,12 @@ __host__ __device__ constexpr int wide_ints(int nk, int J) {
 // by key, 64 keys per pass (a chunk whose keys span more takes more passes).
 // The chunk is laid out in LDS in destination order and written from there,
 // so each key's run in the chunk is stored to consecutive addresses rather
-// than a few records per round.  The next destination of every key lives in
-// one LDS table for the whole tile, started from the tile's scatter bases,
-// so the tile needs no histogram of its own here.  Count entries carry the
-// number of the pass that wrote them, which spares clearing the table
-// between passes.
+// than a few records per round.  The next destination of each key lives in
+// one LDS table for the whole tile, started from the tile's scatter bases
+// (for the keys from the tile's smallest on, as k_count recorded it), so the
+// tile needs no histogram of its own here.  Count entries carry the number
+// of the pass that wrote them, which spares clearing the table between
+// passes.
 template <class R, bool kOpen>
 __global__ __launch_bounds__(kParticleThreads) void k_move_scatter_wide(const InstDesc* __restrict__ descs,
                                                                        const int2* __restrict__ work) {
@@ -830,16 +867,22 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter_wide(const In
     constexpr int G = J * kScatterWaves;
     const int nk = d.nkeys;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    int* run = lds;                    // nk: next destination of each key
-    int* cnt = run + nk;               // G x 64: (pass << 8) | count per group and key
+    // next destination of keys tk0 .. tk0 + nrun - 1 of the tile; keys past
+    // them (a tile spanning more than kWideRunKeys) keep theirs in the
+    // tile's row of the count matrix, updated with atomics
+    const int tk0 = d.tkeys[2 * tile], tk1 = d.tkeys[2 * tile + 1];
+    const int nrun = min(max(tk1 - tk0 + 1, 0), kWideRunKeys);
+    const int nrt = min(nk, kWideRunKeys);  // the table's size in the launch's LDS layout
+    int* run = lds;
+    int* cnt = run + nrt;              // G x 64: (pass << 8) | count per group and key
     int* pre = cnt + G * kWideKeys;    // G x 64: records of the key in earlier groups of the chunk
     int* koff = pre + G * kWideKeys;   // 64: the key's first staging index
     int* dlt = koff + kWideKeys;       // 64: destination minus staging index
     int* red = dlt + kWideKeys;        // chunk key range, two chunks alternating
     int* spos = red + 4;               // C: destination of each staged record
-    R* srec = (R*)(lds + wide_ints(nk, J));  // 4 x C: y, vx, vy, vz in destination order
+    R* srec = (R*)(lds + wide_ints(nrt, J));  // 4 x C: y, vx, vy, vz in destination order
     const gptr<int32_t> brow = gmem(d.counts) + (size_t)tile * nk;
-    for (int c = tid; c < nk; c += kParticleThreads) run[c] = brow[c];
+    for (int c = tid; c < nrun; c += kParticleThreads) run[c] = brow[tk0 + c];
     for (int e = tid; e < G * kWideKeys; e += kParticleThreads) cnt[e] = 0;
     if (tid < 4) red[tid] = (tid & 1) ? -1 : INT32_MAX;
     __syncthreads();
@@ -935,9 +978,15 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter_wide(const In
                 const int ko = nbase + incl - tot;
                 koff[lane] = ko;
                 if (tot > 0) {  // some record has key w0 + lane, so it is < nk
-                    const int r = run[w0 + lane];
+                    const unsigned kr = (unsigned)(w0 + lane - tk0);
+                    int r;
+                    if (kr < (unsigned)nrun) {
+                        r = run[kr];
+                        run[kr] = r + tot;
+                    } else {
+                        r = atomicAdd((int*)(brow + (w0 + lane)), tot);
+                    }
                     dlt[lane] = r - ko;
-                    run[w0 + lane] = r + tot;
                 }
                 nbase += __shfl(incl, 63, 64);
             }
@@ -2582,7 +2631,8 @@ size_t scatter_lds_bytes(Mode mode, int max_cc, int stage_max) {
 size_t wide_scatter_lds_bytes(Mode mode, int max_cc) {
     const int J = mode == kFp32Fast ? kWideRecs32 : kWideRecs64;
     const size_t rb = mode == kFp32Fast ? sizeof(float) : sizeof(double);
-    return (size_t)wide_ints(max_cc, J) * sizeof(int) + (size_t)4 * J * kParticleThreads * rb;
+    const int nrt = max_cc < kWideRunKeys ? max_cc : kWideRunKeys;
+    return (size_t)wide_ints(nrt, J) * sizeof(int) + (size_t)4 * J * kParticleThreads * rb;
 }
 
 size_t bucket_collide_lds_bytes(Mode mode, int cap) {

@@ -55,7 +55,7 @@ struct Plan {
     int32_t tile_items = 256, tiles = 1, nseg = 1;
     double H = 1.0, L = 1.0, lam = 0, dt = 0, g = 0, kntc = 0, crmax0 = 0, sqrt_tw = 1, inv_dy = 0;
     // arena offsets
-    uint64_t off_buf[2][4], off_cell, off_counts, off_segsum, off_kcount, off_koffset, off_count,
+    uint64_t off_buf[2][4], off_cell, off_counts, off_tkeys, off_segsum, off_kcount, off_koffset, off_count,
         off_offset, off_crmax,
         off_rem, off_acc, off_ncoll, off_est, off_sc, off_os, off_desc, total;
 };
@@ -189,6 +189,7 @@ Plan make_plan(const dsmc_params* p) {
         for (int a = 0; a < 4; ++a) q.off_buf[b][a] = take((uint64_t)q.ncap * q.rb);
     q.off_cell = take((uint64_t)q.ncap * 4);
     q.off_counts = take((uint64_t)q.tiles * keys * 4);
+    q.off_tkeys = take((uint64_t)q.tiles * 2 * 4);
     q.off_segsum = take((uint64_t)q.nseg * keys * 4);
     q.off_kcount = take(keys * 4);
     q.off_koffset = take(keys * 4);
@@ -1109,6 +1110,7 @@ int dsmc_create(const dsmc_params* p, void* stream, void* arena, uint64_t arena_
         for (int a = 0; a < 4; ++a) d.buf[b][a] = base + q.off_buf[b][a];
     d.cell = (int32_t*)(base + q.off_cell);
     d.counts = (int32_t*)(base + q.off_counts);
+    d.tkeys = (int32_t*)(base + q.off_tkeys);
     d.segsum = (int32_t*)(base + q.off_segsum);
     d.count = (int32_t*)(base + q.off_count);
     d.offset = (int32_t*)(base + q.off_offset);

@@ -203,13 +203,17 @@ def test_crafted_sort_inputs(D):
         assert np.array_equal(cnt, ocnt) and np.array_equal(off, ooff)
 
 
-def test_wide_tiles_from_unsorted_state_bit_exact(D):
+@pytest.mark.parametrize("cells,ppc", [(300, 500), (1500, 600)])
+def test_wide_tiles_from_unsorted_state_bit_exact(D, cells, ppc):
     """Tiles larger than the move-scatter holds in registers (300 cells of 500:
-    1280-slot tiles, over the 1024 slots the FP64 registers hold) are walked
-    in chunks ranked 64 keys per pass.  From a state in random slot order every
-    chunk spans all 300 keys (five passes), a few cells are crowded and many
-    empty; two full steps must still equal the oracle bit for bit."""
-    p = Params(kn=0.3, body_force=0.01, n_cells=300, particles_per_cell=500, seed=27,
+    1280-slot tiles, over the 1024 slots the FP64 registers hold; 1500 cells
+    of 600: 6144-slot tiles) are walked in chunks ranked 64 keys per pass.
+    From a state in random slot order every chunk spans all keys (5 and 24
+    passes), a few cells are crowded and many empty; with 1500 keys a tile
+    spans more keys than its LDS table holds (1024), and the rest keep their
+    next destinations in global memory.  Two full steps must still equal the
+    oracle bit for bit."""
+    p = Params(kn=0.3, body_force=0.01, n_cells=cells, particles_per_cell=ppc, seed=27,
                n_transient=0, precision=FP64_DETERMINISTIC)
     o = oracle.Oracle(p)
     rng = np.random.default_rng(11)
