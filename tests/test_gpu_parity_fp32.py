@@ -520,6 +520,46 @@ def test_pre_collision_sum_without_collisions_equals_post(D, prec_name, ppc):
     assert np.array_equal(e["pxy_mid"], e["pxy"])
 
 
+@pytest.mark.parametrize("prec_name", ["DSMC_FP32_FAST", "DSMC_FP64_FAST"])
+def test_cell_with_more_than_2_24_candidates(D, prec_name):
+    """A cell whose NTC draws 2^24 candidates or more in one step claims with
+    plain candidate numbers and clears its claims after every round (round
+    stamps cover fewer).  One cell of 8000 particles with a long step has
+    about 2.0e7 candidates; one sort and collide phase (no move) must conserve
+    momentum and energy, and its accepted collisions must match the NTC
+    expectation: M times the mean relative speed of the gas, 4 (T / pi)^1/2
+    for hard spheres at temperature T, over the cell's c_r,max.  FP32
+    stages the cell in LDS (the eight-wavefront workgroup), FP64 works on
+    global memory."""
+    prec = getattr(D, prec_name)
+    p = Params(kn=0.01, body_force=0.0, n_cells=1, particles_per_cell=8000, dt=10.0, seed=61,
+               n_transient=0, precision=prec)
+    # sorted (the cell tables) and collided, not moved
+    mask = D.DSMC_PHASE_SORT | D.DSMC_PHASE_COLLIDE | D.DSMC_PHASE_SAMPLE
+    print(f"cell of 2^24+ candidates: {prec_name}", flush=True)
+    with D.Solver(p, debug_phase_mask=mask) as s:
+        y0, vx0, vy0, vz0, _, _ = s.get_state()
+        crm, rem, _, _ = s.get_cells()
+        crm0, rem0 = crm[0], rem[0]
+        s.step(1)
+        y1, vx1, vy1, vz1, _, _ = s.get_state()
+        e = s.sample()
+    v0 = np.stack([vx0, vy0, vz0]).astype(np.float64)
+    v1 = np.stack([vx1, vy1, vz1]).astype(np.float64)
+    N = v0.shape[1]
+    assert np.array_equal(y0, y1)  # no move
+    assert not np.array_equal(v0, v1)
+    e0, e1 = (v0 ** 2).sum(), (v1 ** 2).sum()
+    assert abs(e1 - e0) < 1e-4 * e0
+    assert np.all(np.abs(v1.sum(axis=1) - v0.sum(axis=1)) < 1e-3 * math.sqrt(e0))
+    kntc = p.dt * p.n_sub / (math.sqrt(2.0) * p.kn * p.particles_per_cell)
+    M = math.floor(0.5 * N * (N - 1) * crm0 * kntc + rem0)
+    assert M >= 2 ** 24
+    T = ((v0 - v0.mean(axis=1, keepdims=True)) ** 2).sum() / (3 * N)
+    expected = M * 4.0 * math.sqrt(T / math.pi) / crm0
+    assert abs(e["n_collisions"] - expected) < 0.02 * expected, (e["n_collisions"], expected)
+
+
 def test_time_centred_stress_keeps_the_momentum_balance(D):
     """The FP32 path's time-centred stress meets dP/dy = 2F in the interior
     (Eqs. 1 and 6), while the stress sampled after the collisions lies about
