@@ -17,6 +17,9 @@ constexpr int kColThreads = 256;       // cells per workgroup of the column-scan
 constexpr int kScanThreads = 1024;     // threads of the per-instance scan kernel
 constexpr int kSegTiles = 32;          // tiles per column-scan segment
 constexpr int kCountScanEntries = 8192;  // largest count matrix (tiles x keys) scanned in LDS
+// largest (segments + 1) x keys of an instance whose three column scans run
+// in one workgroup with its segment sums in LDS
+constexpr int kSegScanEntries = 16384;
 constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
 constexpr int kCoopMin = 256;          // cells this full are collided by a whole workgroup
 constexpr int kGroupTableFactor = 8;   // claim-table entries per lane of a small-cell group

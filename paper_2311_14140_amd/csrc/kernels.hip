@@ -817,6 +817,99 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_small(const InstDesc* __r
     if (tid == 0) advance_step(d);
 }
 
+// The column scans in one workgroup per instance for count matrices too
+// large for LDS whose segment sums fit it (lanes where every instance has at
+// most kSegScanEntries (segments + 1) x keys): the work of k_colsum,
+// k_scan and k_colprefix in one launch.  Items are (64 adjacent keys, one
+// segment of kSegTiles tiles), spread over the wavefronts; each issues its
+// segment's loads before using them.  First the segment sums go to LDS, then
+// each key's exclusive prefix over the segments, its total and offset, and
+// last each tile's scatter bases, written over its counts.
+__global__ __launch_bounds__(kScanThreads) void k_scan_seg(const InstDesc* __restrict__ descs) {
+    extern __shared__ int seg[];  // nseg x keys: segment sums, then their prefixes; then keys: offsets
+    __shared__ int wsum[kScanThreads / 64];
+    __shared__ int sh_used;
+    const InstDesc& d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    constexpr int nw = kScanThreads / 64;
+    const int nk = d.nkeys, T = d.tiles, NS = d.nseg;
+    const int KC = (nk + 63) >> 6, items = KC * NS;
+    int* koff = seg + (size_t)NS * nk;
+    const gptr<int32_t> cnt = gmem(d.counts);
+    if (tid == 0) sh_used = book_injections(d);
+    for (int it = wv; it < items; it += nw) {
+        const int c = (it % KC) * 64 + lane, sg = it / KC;
+        const int t0 = sg * kSegTiles, t1 = min(t0 + kSegTiles, T);
+        int v[kSegTiles];
+#pragma unroll
+        for (int u = 0; u < kSegTiles; ++u) v[u] = (c < nk && t0 + u < t1) ? cnt[(size_t)(t0 + u) * nk + c] : 0;
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < kSegTiles; ++u) sum += v[u];
+        if (c < nk) seg[sg * nk + c] = sum;
+    }
+    __syncthreads();
+    // per key: exclusive prefix over the segments and the total
+    for (int c = tid; c < nk; c += kScanThreads) {
+        int tot = 0;
+        for (int sg = 0; sg < NS; ++sg) {
+            const int x = seg[sg * nk + c];
+            seg[sg * nk + c] = tot;
+            tot += x;
+        }
+        koff[c] = tot;  // the key's total until the scan below
+        d.kcount[c] = tot;
+    }
+    __syncthreads();
+    // exclusive scan of the totals in key order
+    const int per = (nk + kScanThreads - 1) / kScanThreads;
+    const int c0 = min(tid * per, nk), c1 = min(c0 + per, nk);
+    int local = 0;
+    for (int c = c0; c < c1; ++c) local += koff[c];
+    const int incl = wave_incl_scan(local, lane);
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    if (wv == 0) {
+        int x = lane < nw ? wsum[lane] : 0;
+        x = wave_incl_scan(x, lane);
+        if (lane < nw) wsum[lane] = x;
+    }
+    __syncthreads();
+    int run = incl - local + (wv ? wsum[wv - 1] : 0);
+    for (int c = c0; c < c1; ++c) {
+        const int tot = koff[c];
+        koff[c] = run;
+        d.koffset[c] = run;
+        // an open instance's last key holds the particles that left: the
+        // live ones are those before it
+        if (d.open && c == nk - 1) {
+            d.os->n_live = run;
+            d.os->n_deleted += tot;
+        }
+        run += tot;
+    }
+    if (tid == kScanThreads - 1 && wsum[nw - 1] != sh_used) atomicOr(&d.sc->status, 2);
+    __syncthreads();
+    // per-tile scatter bases
+    for (int it = wv; it < items; it += nw) {
+        const int c = (it % KC) * 64 + lane, sg = it / KC;
+        const int t0 = sg * kSegTiles, t1 = min(t0 + kSegTiles, T);
+        int v[kSegTiles];
+#pragma unroll
+        for (int u = 0; u < kSegTiles; ++u) v[u] = (c < nk && t0 + u < t1) ? cnt[(size_t)(t0 + u) * nk + c] : 0;
+        if (c < nk) {
+            int r = koff[c] + seg[sg * nk + c];
+#pragma unroll
+            for (int u = 0; u < kSegTiles; ++u) {
+                if (t0 + u < t1) cnt[(size_t)(t0 + u) * nk + c] = r;
+                r += v[u];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) advance_step(d);
+}
+
 // Records per lane k_move_scatter holds in registers (tiles up to
 // 256 * this many slots take the one-read path).
 template <class R> struct ScatterRegs {
@@ -2546,6 +2639,11 @@ void step_kernels(const Work& w, Mode mode, unsigned phase, hipStream_t st, hipE
             hipLaunchKernelGGL(k_scan_small, dim3(w.n_inst), dim3(kScanThreads),
                                (size_t)w.scan_small_lds, st, w.desc);
             mark(3);
+        } else if (w.scan_seg_lds) {
+            mark(2);
+            hipLaunchKernelGGL(k_scan_seg, dim3(w.n_inst), dim3(kScanThreads), (size_t)w.scan_seg_lds, st,
+                               w.desc);
+            mark(3);
         } else {
             hipLaunchKernelGGL(k_colsum, dim3(w.n_cols), dim3(kColThreads), 0, st, w.desc, w.cols);
             mark(2);
@@ -2694,6 +2792,7 @@ hipError_t configure_kernels(size_t max_dynamic_lds) {
     set((const void*)k_move_scatter_wide<float, true>);
     set((const void*)k_move_scatter_wide<double, true>);
     set((const void*)k_scan_small);
+    set((const void*)k_scan_seg);
     return e;
 }
 

@@ -39,6 +39,9 @@ struct Work {
     // > 0: every instance's count matrix fits one workgroup's LDS, and k_scan_small
     // (this many bytes of it) replaces the three column-scan kernels
     int scan_small_lds;
+    // > 0 (and scan_small_lds 0): every instance's segment sums fit LDS, and
+    // k_scan_seg (this many bytes of it) replaces the three column-scan kernels
+    int scan_seg_lds;
     // dynamic LDS of the count, move-scatter and collide launches is at
     // least this many bytes (0: what they use): it caps how many of their
     // workgroups share a CU, the occupancy knob of the launch-shape tuning

@@ -615,6 +615,17 @@ int build_lane(dsmc_group* g, Lane& lane) {
         scan_small_entries = std::max<int>(scan_small_entries, (int)std::min<int64_t>(e, INT32_MAX));
     }
     const int scan_small_lds = small_counts ? std::max(scan_small_entries, 1) * (int)sizeof(int) : 0;
+    // else in one workgroup per instance with the segment sums in LDS, when
+    // they fit for every instance
+    int scan_seg_entries = 0;
+    bool seg_counts = !small_counts && resident.empty() && n > 0 &&
+                      (g->phase & (DSMC_PHASE_MOVE | DSMC_PHASE_SORT)) == (DSMC_PHASE_MOVE | DSMC_PHASE_SORT);
+    for (const InstDesc& d : descs) {
+        const int64_t e = ((int64_t)d.nseg + 1) * d.nkeys;
+        seg_counts &= e <= kSegScanEntries;
+        scan_seg_entries = std::max<int>(scan_seg_entries, (int)std::min<int64_t>(e, INT32_MAX));
+    }
+    const int scan_seg_lds = seg_counts ? std::max(scan_seg_entries, 1) * (int)sizeof(int) : 0;
 
     auto bytes_of = [](size_t k, size_t sz) { return align_up(sz * std::max<size_t>(k, 1)); };
     const size_t need = bytes_of(n, sizeof(InstDesc)) + bytes_of(tiles.size(), sizeof(int2)) +
@@ -673,6 +684,7 @@ int build_lane(dsmc_group* g, Lane& lane) {
     w.n_resident = (int)resident.size();
     w.resident_cap = resident_cap;
     w.scan_small_lds = scan_small_lds;
+    w.scan_seg_lds = scan_seg_lds;
     // occupancy cap: the count, move-scatter and collide workgroups are 4
     // wavefronts; asking each for 1/k of the CU's LDS (less a margin for
     // static shared variables and allocation granularity) lets at most k
@@ -1450,7 +1462,8 @@ int dsmc_profile_step(dsmc_handle* h, int64_t n_steps, double* phase_ms) {
             // and prefixes
             const Work& w = g->lanes[b % nl].work;
             for (int i = 0; i < 6; ++i) {
-                if ((w.n_resident && i < 5) || (w.scan_small_lds && (i == 1 || i == 3))) continue;
+                if ((w.n_resident && i < 5) || ((w.scan_small_lds || w.scan_seg_lds) && (i == 1 || i == 3)))
+                    continue;
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, ev[7 * b + i], ev[7 * b + i + 1]) == hipSuccess) {
                     acc[i] += ms;

@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # kernel name prefix -> step slot (the slots of dsmc_profile_step; a resident
 # lane's whole-step kernel is kept apart, as that call reports its share)
 PHASE_OF = (("k_count", "count"), ("k_colsum", "colsum"), ("k_scan_small", "scan"),
+            ("k_scan_seg", "scan"),
             ("k_scan", "scan"), ("k_colprefix", "colprefix"), ("k_move_scatter", "move_scatter"),
             ("k_move_scatter_wide", "move_scatter"),
             ("k_collide_bucket", "collide"), ("k_collide_fast", "collide"),
