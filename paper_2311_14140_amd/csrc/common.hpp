@@ -20,6 +20,7 @@ constexpr int kCountScanEntries = 8192;  // largest count matrix (tiles x keys) 
 // largest (segments + 1) x keys of an instance whose three column scans run
 // in one workgroup with its segment sums in LDS
 constexpr int kSegScanEntries = 16384;
+constexpr int kSegScanMinInstances = 4;  // instances a lane needs for that scan
 constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
 constexpr int kCoopMin = 256;          // cells this full are collided by a whole workgroup
 constexpr int kGroupTableFactor = 8;   // claim-table entries per lane of a small-cell group

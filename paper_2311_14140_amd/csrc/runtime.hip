@@ -616,9 +616,12 @@ int build_lane(dsmc_group* g, Lane& lane) {
     }
     const int scan_small_lds = small_counts ? std::max(scan_small_entries, 1) * (int)sizeof(int) : 0;
     // else in one workgroup per instance with the segment sums in LDS, when
-    // they fit for every instance
+    // they fit for every instance and the lane has instances enough to fill
+    // the device with such workgroups (one instance's column kernels spread
+    // its segments over many workgroups, and were faster alone: 46 against
+    // 52 us per step of the Kn 0.1 instance)
     int scan_seg_entries = 0;
-    bool seg_counts = !small_counts && resident.empty() && n > 0 &&
+    bool seg_counts = !small_counts && resident.empty() && n >= kSegScanMinInstances &&
                       (g->phase & (DSMC_PHASE_MOVE | DSMC_PHASE_SORT)) == (DSMC_PHASE_MOVE | DSMC_PHASE_SORT);
     for (const InstDesc& d : descs) {
         const int64_t e = ((int64_t)d.nseg + 1) * d.nkeys;
