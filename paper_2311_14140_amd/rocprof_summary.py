@@ -1,12 +1,15 @@
 """Summaries of rocprofv3 output for the kernels of a DSMC step.
 
-    python -m paper_2311_14140_amd.rocprof_summary stats DIR
+    python -m paper_2311_14140_amd.rocprof_summary stats DIR [--last N]
     python -m paper_2311_14140_amd.rocprof_summary traffic --stats DIR --fetch DIR \\
         --write DIR --tag NAME --workload TEXT [--copy-mib 256] [--json FILE]
     python -m paper_2311_14140_amd.rocprof_summary issue DIR [DIR ...]
 
 ``stats`` prints the kernel statistics of a ``--kernel-trace --stats -f csv``
-run as a table.  ``traffic`` reads two counter runs (``--pmc FETCH_SIZE`` and
+run as a table; with ``--last N`` it averages only each step kernel's last N
+dispatches from the kernel trace (bench.py's per-kernel profile launches
+its steps last, one lane after another, where the timed graph replays run
+the lanes concurrently).  ``traffic`` reads two counter runs (``--pmc FETCH_SIZE`` and
 ``--pmc WRITE_SIZE``, each in its own run) and converts each kernel's average
 KiB per dispatch to bytes, scaled by what the same counter reads for a plain
 device copy of known size in the same run (the bench's calibration copy):
@@ -148,7 +151,31 @@ def cmd_issue(a):
             print("  instructions per wavefront: " + line)
 
 
+def last_dispatches(directory: str, last: int):
+    """[(name, dispatches averaged, average ns)] over each step kernel's last
+    `last` dispatches of a kernel trace (not the estimators' kernel, and not
+    a resident lane's, whose launches carry different numbers of steps)."""
+    per = defaultdict(list)
+    for r in _rows(directory, "kernel_trace.csv"):
+        if phase(r["Kernel_Name"]) not in (None, "finalize", "resident"):
+            per[r["Kernel_Name"]].append((int(r["Dispatch_Id"]),
+                                          int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = []
+    for name, ds in per.items():
+        ds.sort()
+        tail = [t for _, t in ds[-last:]]
+        out.append((name, len(tail), sum(tail) / len(tail)))
+    out.sort(key=lambda x: -x[2] * x[1])
+    return out
+
+
 def cmd_stats(a):
+    if a.last:
+        print(f"| kernel | last dispatches | average us |")
+        print("|---|---|---|")
+        for name, n, avg in last_dispatches(a.dir, a.last):
+            print(f"| {short_name(name)} | {n} | {avg / 1e3:.3f} |")
+        return
     print("| kernel | calls | total us | average us | % |")
     print("|---|---|---|---|---|")
     for name, calls, tot, avg, pct in kernel_stats(a.dir):
@@ -208,6 +235,7 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
     s.add_argument("dir")
+    s.add_argument("--last", type=int, default=0)
     t = sub.add_parser("traffic")
     t.add_argument("--stats", required=True)
     t.add_argument("--fetch", required=True)
