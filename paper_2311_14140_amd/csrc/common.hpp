@@ -21,7 +21,7 @@ constexpr int kCountScanEntries = 8192;  // largest count matrix (tiles x keys) 
 // in one workgroup with its segment sums in LDS
 constexpr int kSegScanEntries = 16384;
 constexpr int kSegScanMinInstances = 4;  // instances a lane needs for that scan
-constexpr int kFastWaves = 4;          // wavefronts per fast-collide workgroup
+constexpr int kFastWaves = 4;          // wavefronts per bucket-collide workgroup
 constexpr int kCoopMin = 256;          // cells this full are collided by a whole workgroup
 constexpr int kGroupTableFactor = 8;   // claim-table entries per lane of a small-cell group
 // wavefronts of a workgroup-collide workgroup: 4, or 8 when its staged
