@@ -46,11 +46,38 @@ PHASE_OF = (("k_count", "count"), ("k_colsum", "colsum"), ("k_scan_small", "scan
 SOURCES = ("kernels.hip", "runtime.hip", "rng.hpp", "common.hpp", "kernels.hpp")
 
 
+def _code_only(text: str) -> str:
+    """The source without its comments and with whitespace runs collapsed, so
+    that a change of comments alone keeps the hash (string and character
+    literals are kept as they are)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        ch = text[i]
+        if ch in "\"'":
+            j = i + 1
+            while j < n and text[j] != ch:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(ch)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_hash() -> str:
+    """Hash of the kernel and runtime sources' code (comments excluded)."""
     h = hashlib.sha256()
     for f in SOURCES:
-        with open(os.path.join(ROOT, "paper_2311_14140_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2311_14140_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -218,7 +245,7 @@ def cmd_traffic(a):
         rec["fetch_KiB"][ph], rec["write_KiB"][ph] = fk, wk
         rec["bytes_per_launch"][ph] = b
         print(f"| {ph} | {fk:.1f} | {wk:.1f} | {b / 1e6:.3f} |")
-    print(f"\nKernel source hash: {rec['kernel_source_hash']}")
+    print(f"\nKernel source hash (code without comments): {rec['kernel_source_hash']}")
     if a.json:
         data = {}
         if os.path.exists(a.json):

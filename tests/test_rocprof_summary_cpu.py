@@ -63,3 +63,12 @@ def test_last_dispatches_average_the_tail(tmp_path):
     _write(tmp_path / "k" / "x_kernel_trace.csv", hdr, rows)
     got = rs.last_dispatches(str(tmp_path / "k"), 3)
     assert got == [("k_count<float, false>", 3, 300.0)]
+
+
+def test_source_hash_ignores_comments_only():
+    a = 'int f(int x) { // add one\n  return x + 1; /* done */ }\nconst char* s = "a // b";'
+    b = 'int f(int x) {\n    return x + 1;   }\n// another note\nconst char* s = "a // b";'
+    c = 'int f(int x) { return x + 2; }\nconst char* s = "a // b";'
+    assert rs._code_only(a) == rs._code_only(b)
+    assert rs._code_only(a) != rs._code_only(c)
+    assert '"a // b"' in rs._code_only(a)
