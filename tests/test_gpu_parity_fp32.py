@@ -345,19 +345,25 @@ def test_autotune_choice_valid_and_results_unchanged(D):
     g.close()
 
 
-def test_collide_global_fallback_equals_staged(D):
+@pytest.mark.parametrize("prec_name,ppc,big_ppc", [("DSMC_FP32_FAST", 300, 9000),
+                                                    ("DSMC_FP64_FAST", 150, 4000)])
+def test_collide_global_fallback_equals_staged(D, prec_name, ppc, big_ppc):
     """A cell far fuller than the staging room of its instance is collided on
-    global memory; inside a group whose staging room fits it, the same cell
-    is staged in LDS.  Both give identical results."""
-    a = Params(kn=0.5, body_force=0.01, n_cells=20, particles_per_cell=300, seed=71,
-               n_transient=0, precision=D.DSMC_FP32_FAST)
-    big = Params(kn=0.5, body_force=0.01, n_cells=1, particles_per_cell=9000, seed=72,
-                 n_transient=0, precision=D.DSMC_FP32_FAST)
+    global memory by a four-wavefront workgroup; inside a group whose staging
+    room fits it (a member with cells filling more than half of a CU's LDS),
+    the same cell is staged in LDS and collided by an eight-wavefront
+    workgroup.  Both give identical results, in FP32 and in FP64."""
+    prec = getattr(D, prec_name)
+    a = Params(kn=0.5, body_force=0.01, n_cells=20, particles_per_cell=ppc, seed=71,
+               n_transient=0, precision=prec)
+    big = Params(kn=0.5, body_force=0.01, n_cells=1, particles_per_cell=big_ppc, seed=72,
+                 n_transient=0, precision=prec)
+    dt = np.float32 if prec == D.DSMC_FP32_FAST else np.float64
     rng = np.random.default_rng(5)
 
     def crafted(s):
-        y = (0.02 + 0.01 * rng.random(s.N)).astype(np.float32)  # every particle in cell 0
-        v = rng.normal(size=(3, s.N)).astype(np.float32)
+        y = (0.02 + 0.01 * rng.random(s.N)).astype(dt)  # every particle in cell 0
+        v = rng.normal(size=(3, s.N)).astype(dt)
         return y, v
 
     with D.Solver(a) as s1:
@@ -671,6 +677,37 @@ def test_moment_sums_match_the_particle_state(D, prec_name, ppc):
         want = np.bincount(cell, weights=t, minlength=raw.shape[0])
         scale = np.bincount(cell, weights=np.abs(t), minlength=raw.shape[0])
         assert np.all(np.abs(raw[:, k] - want) <= 1e-12 * scale + 1e-300), k
+
+
+@pytest.mark.parametrize("prec_name", ["DSMC_FP32_FAST", "DSMC_FP64_FAST"])
+def test_large_tiles_equal_held_tiles_open_patch(D, prec_name):
+    """An open patch (full cells, Chapman-Enskog inflow, particles injected
+    and removed every step) on tiles eight times larger than its automatic
+    ones takes the wide-tile scatter with the open boundary's extra key;
+    states, live counts, boundary counters and window sums equal the
+    automatic tiles' bit for bit."""
+    prec = getattr(D, prec_name)
+    p = Params(kn=0.05, body_force=0.01, n_cells=30, particles_per_cell=300, seed=33,
+               n_transient=3, domain_length=0.3, precision=prec)
+    out = []
+    for tile_mult in (1, 8):
+        g = D.Group()
+        s = D.Solver(p)
+        s.set_inflow(u=0.08, dudy=0.3)
+        g.add(s)
+        g.set_tuning(tile_mult, 0, 0)
+        g.step(17)
+        g.sync()
+        out.append((s.get_state(), s.get_cells(), s.sample(raw=True)["raw"], s.open_state()))
+        g.close()
+        s.close()
+    (sa, ca, ra, oa), (sb, cb, rb, ob) = out
+    for a, b in zip(sa, sb):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+    for a, b in zip(ca, cb):
+        assert np.array_equal(a, b)
+    assert np.array_equal(ra, rb)
+    assert oa == ob and oa["n_injected"] > 0 and oa["n_deleted"] > 0
 
 
 @pytest.mark.parametrize("prec_name", ["DSMC_FP32_FAST", "DSMC_FP64_FAST"])
