@@ -65,24 +65,6 @@ __device__ __forceinline__ unsigned long long lanes_below(int lane) {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// The lanes of the wavefront whose key equals this lane's, among the lanes
-// with `valid` set (keys of nbits bits).  One ballot per key bit separates
-// the keys; a wavefront whose valid lanes all hold one key (the common case
-// for input already sorted by key) skips the bits.  Only valid lanes' results
-// are meaningful.
-__device__ __forceinline__ unsigned long long same_key_lanes(bool valid, int key, int nbits) {
-    const unsigned long long m = __ballot(valid);
-    const int k0 = __builtin_amdgcn_readfirstlane(key);
-    if (__ballot(valid && key != k0) == 0ull) return m;
-    unsigned long long r = m;
-    for (int b = 0; b < nbits; ++b) {
-        const bool bit = (key >> b) & 1;
-        const unsigned long long bal = __ballot(bit);
-        r &= bit ? bal : ~bal;
-    }
-    return r;
-}
-
 // ------------------------------------------------------------------ init
 // Initial state (the paper's gas at rest between the plates, Sec. 2.1):
 // particle p sits in sampling cell p / ppc, uniform inside it, with a
@@ -636,7 +618,12 @@ __global__ __launch_bounds__(kParticleThreads) void k_scatter(const InstDesc* __
             rvy = src.vy[i];
             rvz = src.vz[i];
         }
-        const unsigned long long m = same_key_lanes(valid, c, nbits);
+        unsigned long long m = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (c >> b) & 1;
+            const unsigned long long bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
         if (valid) {
             const int pos = mine[c] + __popcll(m & lt);
             // every lane of the group reads the base before its leader
@@ -1062,7 +1049,13 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter_wide(const In
             for (int j = 0; j < J; ++j) {
                 const int kl = key[j] - w0;
                 const bool in = key[j] >= 0 && kl >= 0 && kl < kWideKeys;
-                const unsigned long long m = same_key_lanes(in, kl, 6);
+                unsigned long long m = __ballot(in);
+#pragma unroll
+                for (int b = 0; b < 6; ++b) {
+                    const bool bit = (kl >> b) & 1;
+                    const unsigned long long bal = __ballot(bit);
+                    m &= bit ? bal : ~bal;
+                }
                 rank[j] = __popcll(m & lt);
                 if (in && rank[j] == 0) cnt[(j * kScatterWaves + wv) * kWideKeys + kl] = (pass << 8) | __popcll(m);
             }
@@ -1288,7 +1281,12 @@ __global__ __launch_bounds__(kParticleThreads) void k_move_scatter(const InstDes
     const int n_tile = end - start;
     // rank one round of 64 slots and place the records
     auto place = [&](bool valid, int kk, R y, R vx, R vy, R vz) {
-        const unsigned long long m = same_key_lanes(valid, kk, nbits);
+        unsigned long long m = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (kk >> b) & 1;
+            const unsigned long long bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
         if (valid) {
             int pos = mine[kk] + __popcll(m & lt);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -2029,7 +2027,12 @@ __device__ __forceinline__ void bucket_sort(const InstDesc& d, const P4<R>& g, i
             rz = g.vz[s0 + i];
             lc = cell_of<R>(d, ry) - c0;
         }
-        const unsigned long long m = same_key_lanes(valid, lc, nbits);
+        unsigned long long m = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (lc >> b) & 1;
+            const unsigned long long bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
         if (valid) {
             const int pos = mine[lc] + __popcll(m & lt);
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -2111,7 +2114,12 @@ __device__ __forceinline__ void bucket_sort_regs(const InstDesc& d, const P4<R>&
     for (int k = 0; k < K; ++k) {
         if (q0 + 64 * k < q1) {  // uniform over the wavefront
             const bool valid = q0 + 64 * k + lane < q1;
-            const unsigned long long m = same_key_lanes(valid, lc[k], nbits);
+            unsigned long long m = __ballot(valid);
+            for (int b = 0; b < nbits; ++b) {
+                const bool bit = (lc[k] >> b) & 1;
+                const unsigned long long bal = __ballot(bit);
+                m &= bit ? bal : ~bal;
+            }
             if (valid) {
                 const int pos = mine[lc[k]] + __popcll(m & lt);
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -2430,7 +2438,12 @@ __global__ __launch_bounds__(64 * kResidentWaves) void k_resident(const InstDesc
         for (int k = 0; k < K; ++k) {
             if (q0 + 64 * k < q1) {  // uniform over the wavefront
                 const bool valid = q0 + 64 * k + lane < q1;
-                const unsigned long long m = same_key_lanes(valid, key[k], nbits);
+                unsigned long long m = __ballot(valid);
+                for (int b = 0; b < nbits; ++b) {
+                    const bool bit = (key[k] >> b) & 1;
+                    const unsigned long long bal = __ballot(bit);
+                    m &= bit ? bal : ~bal;
+                }
                 if (valid) {
                     int pos = mine[key[k]] + __popcll(m & lt);
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
