@@ -354,6 +354,7 @@ struct dsmc_group {
     unsigned phase = DSMC_PHASE_ALL;
     int n_lanes = 1;     // lanes in use (lanes.size() may be larger)
     int resident_lane = -1;  // the lane of the small members of a mixed group, or -1
+    std::vector<int> lane_order;  // enqueue order of the lanes: resident ones first
     std::vector<Lane> lanes;
     hipEvent_t fork = nullptr;
     // dsmc_group_sample: the members' descriptors and staging-block offsets
@@ -796,6 +797,13 @@ int rebuild(dsmc_group* g) {
         r = capture_lane(g, g->lanes[k]);
         if (r) return r;
     }
+    // resident lanes are enqueued first (kept here, so that stepping
+    // allocates nothing on the host)
+    g->lane_order.clear();
+    for (int k = 0; k < nl; ++k)
+        if (g->lanes[k].work.n_resident) g->lane_order.push_back(k);
+    for (int k = 0; k < nl; ++k)
+        if (!g->lanes[k].work.n_resident) g->lane_order.push_back(k);
     g->dirty = false;
     return DSMC_OK;
 }
@@ -814,13 +822,7 @@ int enqueue_steps(dsmc_group* g, int64_t n_steps) {
     // of a CU's LDS, which a CU has free before the multi-kernel lanes fill
     // it; enqueued after them, they could only start in the gaps between
     // those lanes' kernels and finished after them
-    std::vector<int> order;
-    order.reserve(nl);
-    for (int li = 0; li < nl; ++li)
-        if (g->lanes[li].work.n_resident) order.push_back(li);
-    for (int li = 0; li < nl; ++li)
-        if (!g->lanes[li].work.n_resident) order.push_back(li);
-    for (int li : order) {
+    for (int li : g->lane_order) {
         Lane& l = g->lanes[li];
         const hipStream_t st = lane_stream(g, l);
         if (nl > 1) HIP_TRY(&g->err, hipStreamWaitEvent(st, g->fork, 0));
