@@ -1364,6 +1364,8 @@ __device__ __forceinline__ void mom_zero(Mom& m) {
     for (int k = 0; k < kMoments; ++k) m.s[k] = 0.0;
 }
 
+// The deterministic mode's sums: separate products and additions, each
+// rounded, as the sequential reference adds them.
 __device__ __forceinline__ void mom_add(Mom& m, double x, double y, double z) {
     const double v2 = (x * x + y * y) + z * z;
     m.s[0] += 1.0;
@@ -1378,6 +1380,26 @@ __device__ __forceinline__ void mom_add(Mom& m, double x, double y, double z) {
     m.s[9] += y * z;
     m.s[10] += v2 * x;
     m.s[11] += v2 * y;
+}
+
+// The fast modes' sums: each product added with one fused multiply-add (one
+// rounding instead of two, and half the FP64 instructions of the sampling).
+// The stress sum before the collisions is fused the same way, so that with no
+// collision it equals the vxvy sum after them to the last bit.
+__device__ __forceinline__ void mom_add_fused(Mom& m, double x, double y, double z) {
+    const double v2 = __builtin_fma(x, x, __builtin_fma(y, y, z * z));
+    m.s[0] += 1.0;
+    m.s[1] += x;
+    m.s[2] += y;
+    m.s[3] += z;
+    m.s[4] = __builtin_fma(x, x, m.s[4]);
+    m.s[5] = __builtin_fma(y, y, m.s[5]);
+    m.s[6] = __builtin_fma(z, z, m.s[6]);
+    m.s[7] = __builtin_fma(x, y, m.s[7]);
+    m.s[8] = __builtin_fma(x, z, m.s[8]);
+    m.s[9] = __builtin_fma(y, z, m.s[9]);
+    m.s[10] = __builtin_fma(v2, x, m.s[10]);
+    m.s[11] = __builtin_fma(v2, y, m.s[11]);
 }
 
 // ------------------------------------------------ collide (deterministic)
@@ -1686,17 +1708,27 @@ __device__ void coop_ntc(const InstDesc& d, uint32_t s, int c, int nc, int o, V 
 
 // Sampling sums of one cell: per lane over a strided share of the cell, then
 // a fixed butterfly over the wavefront (and, in workgroup mode, the wavefront
-// partials added in wavefront order).
+// partials added in wavefront order).  With store set, each velocity read is
+// also written to the same index of wx, wy, wz (the staged block's copy back
+// to global memory, done in the same pass).
 template <class R, class V, int U = 1>
 __device__ __forceinline__ void cell_moments(V vx, V vy, V vz, int o, int nc, int first,
-                                             int stride, double pre, double tot[kMoments]) {
+                                             int stride, double pre, double tot[kMoments],
+                                             bool store, gptr<R> wx, gptr<R> wy, gptr<R> wz) {
     Mom m;
     mom_zero(m);
     // unrolled U times (when registers allow) so that the next records'
     // loads overlap this one's sums; the order of the additions is unchanged
 #pragma unroll U
-    for (int q = first; q < nc; q += stride)
-        mom_add(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
+    for (int q = first; q < nc; q += stride) {
+        const R x = vx[o + q], y = vy[o + q], z = vz[o + q];
+        if (store) {
+            wx[o + q] = x;
+            wy[o + q] = y;
+            wz[o + q] = z;
+        }
+        mom_add_fused(m, (double)x, (double)y, (double)z);
+    }
     m.s[kMomPreXY] = pre;
 #pragma unroll
     for (int k = 0; k < kMoments; ++k) tot[k] = wave_sum_fixed(m.s[k]);
@@ -1705,18 +1737,24 @@ __device__ __forceinline__ void cell_moments(V vx, V vy, V vz, int o, int nc, in
 // The cells [c0, c1) of a staged block, one at a time with the whole
 // workgroup.  Inlined once for velocities in LDS and once for velocities in
 // global memory, so each copy addresses its memory directly (LDS accesses
-// become ds_* instructions rather than flat ones).
+// become ds_* instructions rather than flat ones).  With wb set (a staged
+// block whose cells are sampled) each cell's velocities are copied back to
+// wx, wy, wz (global, indexed like vx, vy, vz) once its collisions are done:
+// by the sampling threads as they read them, or, in a workgroup wider than
+// those, by the other wavefronts meanwhile.
 template <class R, class V, int U>
 __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int c0, int c1,
                                               int s0, V vx, V vy, V vz, uint32_t* claims,
                                               int tab_mask, CoopShared& sh, bool do_collide,
-                                              bool sample) {
+                                              bool sample, bool wb, gptr<R> wx, gptr<R> wy,
+                                              gptr<R> wz) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // the sampling sums are added by the first kCoopWaves wavefronts in the
     // same order whatever the workgroup's width, so that the width (chosen
     // per launch from the LDS a block needs) changes no sum
     constexpr int nt = 64 * kCoopWaves;
     const bool adds = (int)threadIdx.x < nt;
+    const bool wide = (int)blockDim.x > nt;
     int rnd = 0;  // NTC rounds since the claim table was last clear
     for (int c = c0; c < c1; ++c) {
         const int nc = d.count[c];
@@ -1727,7 +1765,7 @@ __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int
         if (sample) {
             if (adds) {
 #pragma unroll U
-                for (int q = (int)threadIdx.x; q < nc; q += nt) pre += (double)vx[o + q] * (double)vy[o + q];
+                for (int q = (int)threadIdx.x; q < nc; q += nt) pre = __builtin_fma((double)vx[o + q], (double)vy[o + q], pre);
             }
             __syncthreads();
         }
@@ -1735,9 +1773,16 @@ __device__ __forceinline__ void collide_cells(const InstDesc& d, uint32_t s, int
         if (sample) {
             if (adds) {
                 double tot[kMoments];
-                cell_moments<R, V, U>(vx, vy, vz, o, nc, (int)threadIdx.x, nt, pre, tot);
+                cell_moments<R, V, U>(vx, vy, vz, o, nc, (int)threadIdx.x, nt, pre, tot, wb && !wide,
+                                      wx, wy, wz);
                 if (lane == 0)
                     for (int k = 0; k < kMoments; ++k) sh.mom[wv][k] = tot[k];
+            } else if (wb) {
+                for (int q = (int)threadIdx.x - nt; q < nc; q += (int)blockDim.x - nt) {
+                    wx[o + q] = vx[o + q];
+                    wy[o + q] = vy[o + q];
+                    wz[o + q] = vz[o + q];
+                }
             }
             __syncthreads();
             if (threadIdx.x == 0) {
@@ -1800,10 +1845,12 @@ __global__ __launch_bounds__(64 * W) void k_collide_fast(const InstDesc* __restr
         __syncthreads();
         // a workgroup alone on its CU has registers to spare for unrolling
         // the sampling loops; four-wavefront ones keep more workgroups
+        const bool wb = do_collide && sample;
         collide_cells<R, R*, W == kCoopWavesAlone ? 4 : 1>(d, (uint32_t)s, c0, c1, s0, vx, vy, vz, claims,
-                                                           kTable - 1, sh, do_collide, sample);
+                                                           kTable - 1, sh, do_collide, sample, wb,
+                                                           g.vx + s0, g.vy + s0, g.vz + s0);
         __syncthreads();
-        if (do_collide) {
+        if (do_collide && !wb) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 g.vx[s0 + i] = vx[i];
                 g.vy[s0 + i] = vy[i];
@@ -1814,7 +1861,8 @@ __global__ __launch_bounds__(64 * W) void k_collide_fast(const InstDesc* __restr
         // a block fuller than the staging room works on global memory
         __syncthreads();
         collide_cells<R, gptr<R>, 1>(d, (uint32_t)s, c0, c1, s0, g.vx + s0, g.vy + s0, g.vz + s0,
-                                  claims, kTable - 1, sh, do_collide, sample);
+                                  claims, kTable - 1, sh, do_collide, sample, false, g.vx, g.vy,
+                                  g.vz);
     }
 }
 
@@ -1888,7 +1936,7 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
         // before the first candidate runs, so no collision write precedes it)
         double pre = 0.0;
         if (has && sample)
-            for (int q = lane - grp * G; q < nc; q += G) pre += (double)vx[o + q] * (double)vy[o + q];
+            for (int q = lane - grp * G; q < nc; q += G) pre = __builtin_fma((double)vx[o + q], (double)vy[o + q], pre);
         const R crmr = (R)crm0;
         R lane_max = R(0);
         uint32_t lane_coll = 0;
@@ -1933,7 +1981,7 @@ __device__ __forceinline__ void group_cells(const InstDesc& d, uint32_t s, int c
         mom_zero(m);
         if (has && sample)
             for (int q = lane - grp * G; q < nc; q += G)
-                mom_add(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
+                mom_add_fused(m, (double)vx[o + q], (double)vy[o + q], (double)vz[o + q]);
         m.s[kMomPreXY] = pre;
         for (int off = G >> 1; off >= 1; off >>= 1) {
             const double other = __shfl_xor(mx, off, 64);
