@@ -526,29 +526,42 @@ def test_pre_collision_sum_without_collisions_equals_post(D, prec_name, ppc):
     assert np.array_equal(e["pxy_mid"], e["pxy"])
 
 
-@pytest.mark.parametrize("prec_name,ppc,n_sub", [("DSMC_FP32_FAST", 60, 1),
-                                                   ("DSMC_FP32_FAST", 1000, 1),
-                                                   ("DSMC_FP32_FAST", 20000, 2),
-                                                   ("DSMC_FP64_FAST", 1000, 1),
-                                                   ("DSMC_FP64_FAST", 8000, 2)])
-def test_sampling_leaves_the_state_unchanged(D, prec_name, ppc, n_sub):
+@pytest.mark.parametrize("prec_name,ppc,n_sub,ppb", [("DSMC_FP32_FAST", 60, 1, 0),
+                                                       ("DSMC_FP32_FAST", 1000, 1, 0),
+                                                       ("DSMC_FP32_FAST", 1000, 1, 4096),
+                                                       ("DSMC_FP32_FAST", 20000, 2, 0),
+                                                       ("DSMC_FP64_FAST", 1000, 1, 0),
+                                                       ("DSMC_FP64_FAST", 8000, 2, 0)])
+def test_sampling_leaves_the_state_unchanged(D, prec_name, ppc, n_sub, ppb):
     """A sampled step and an unsampled one move and collide the particles
     alike: the state after three steps with every step sampled equals, bit
     for bit, the state after three steps inside the transient.  The cases
     take the small-cell bucket path, four-wavefront workgroups on LDS
-    (1000 per cell) and eight-wavefront ones (cells of 10^4 FP32 or 4000
-    FP64 particles), whose sampling pass also copies the collided block back
-    to global memory."""
+    (1000 per cell; with ppb set, blocks of several cells, packed up to
+    that many particles by the group's tuning) and eight-wavefront ones
+    (cells of 10^4 FP32 or 4000 FP64 particles), whose sampling pass also
+    copies the collided block back to global memory."""
     prec = getattr(D, prec_name)
     p = Params(kn=0.05, body_force=0.01, n_cells=8, particles_per_cell=ppc, seed=43,
                n_transient=0, precision=prec, n_sub=n_sub)
     out = []
     for nt in (0, 100):
-        with D.Solver(p.with_(n_transient=nt)) as s:
+        s = D.Solver(p.with_(n_transient=nt))
+        g = None
+        if ppb:
+            g = D.Group()
+            g.add(s)
+            g.set_tuning(particles_per_block=ppb)
+            g.step(3)
+            g.sync()
+        else:
             s.step(3)
-            st = s.get_state()
-            e = s.sample()
-            out.append(([np.asarray(a).copy() for a in st], e["n_sampled_steps"]))
+        st = s.get_state()
+        e = s.sample()
+        out.append(([np.asarray(a).copy() for a in st], e["n_sampled_steps"]))
+        if g is not None:
+            g.close()
+        s.close()
     assert out[0][1] >= 2 and out[1][1] == 0
     for a, b in zip(out[0][0], out[1][0]):
         assert np.array_equal(a, b)
